@@ -1,0 +1,196 @@
+"""CPU oracle for Parallel Space Saving -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never does, and the
+two share no code.
+
+``pss_oracle.c`` is a plain single-threaded C statement of Algorithm 1
+(ParallelSpaceSaving) and Algorithm 2 (COMBINE) of the paper; this module
+builds it with gcc and wraps it with ctypes.  ``brute.py`` is a second,
+independent pure-Python statement used on tiny inputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pss_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+# 24-byte entry: item, reserved, count, error (same layout as the C struct)
+ENTRY = np.dtype([("item", "<u4"), ("reserved", "<u4"), ("count", "<u8"), ("error", "<u8")])
+
+
+def build(force: bool = True) -> str:
+    """Compile pss_oracle.c with gcc into liboracle.so (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-shared", "-fPIC", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        vp = ctypes.c_void_p
+        u32, u64 = ctypes.c_uint32, ctypes.c_uint64
+        u32p, u64p = ctypes.POINTER(u32), ctypes.POINTER(u64)
+        lib.oracle_space_saving.argtypes = [vp, u64, u32, vp, u32p, u64p]
+        lib.oracle_combine.argtypes = [vp, u32, u64, vp, u32, u64, u32, vp, u32p, u64p]
+        lib.oracle_summary.argtypes = [vp, u64, u32, u32, vp, u32p, u64p]
+        lib.oracle_tree.argtypes = [vp, vp, vp, u32, u32]
+        lib.oracle_run.argtypes = [vp, u64, u32, u32, vp, u32p]
+        lib.oracle_chunk_begin.restype = u64
+        lib.oracle_chunk_begin.argtypes = [u64, u32, u32]
+        lib.oracle_sort_canonical.argtypes = [vp, u32]
+        lib.oracle_prune_threshold.restype = u32
+        lib.oracle_prune_threshold.argtypes = [vp, u32, u64, u32]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _items(items) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(items, dtype=np.uint32))
+    return a
+
+
+class Summary:
+    """A summary: entries (ENTRY array, <= k), its minimum m (0 when not
+    full), k and the stream length N it covers."""
+
+    def __init__(self, k: int, entries=None, m: int = 0, n: int = 0):
+        self.k = int(k)
+        self.entries = np.zeros(0, dtype=ENTRY) if entries is None else entries
+        self.m = int(m)
+        self.n = int(n)
+
+    def canonical(self) -> np.ndarray:
+        e = self.entries.copy()
+        if len(e):
+            _load().oracle_sort_canonical(_ptr(e), len(e))
+        return e
+
+    def as_tuples(self):
+        return [(int(e["item"]), int(e["count"]), int(e["error"])) for e in self.canonical()]
+
+    def query_majority(self) -> np.ndarray:
+        """Entries with count * k > N in canonical order (Algorithm 1, Pruned)."""
+        e = self.entries.copy()
+        q = _load().oracle_prune_threshold(_ptr(e), len(e), self.n, self.k) if len(e) else 0
+        return e[:q]
+
+    def query_topk(self, t: int) -> np.ndarray:
+        return self.canonical()[:t]
+
+    # S <- COMBINE(S, tree(batch)); an empty S is COMBINE's identity
+    def update(self, items, chunks: int) -> "Summary":
+        b = summary(items, self.k, chunks)
+        merged = combine(self, b)
+        merged.n = self.n + b.n
+        self.entries, self.m, self.n = merged.entries, merged.m, merged.n
+        return self
+
+    def merge(self, other: "Summary") -> "Summary":
+        if other.k != self.k:
+            raise ValueError("k mismatch")
+        merged = combine(self, other)
+        self.entries, self.m, self.n = merged.entries, merged.m, self.n + other.n
+        return self
+
+
+def space_saving(items, k: int) -> Summary:
+    """Sequential Space Saving over items with k counters (Section 3)."""
+    a = _items(items)
+    out = np.zeros(max(k, 1), dtype=ENTRY)
+    size, m = ctypes.c_uint32(), ctypes.c_uint64()
+    rc = _load().oracle_space_saving(_ptr(a), len(a), k, _ptr(out), ctypes.byref(size), ctypes.byref(m))
+    if rc != 0:
+        raise RuntimeError("oracle_space_saving: %d" % rc)
+    return Summary(k, out[: size.value].copy(), m.value, len(a))
+
+
+def combine(s1: Summary, s2: Summary) -> Summary:
+    """COMBINE(S1, S2) with Prune(k) (Algorithm 2)."""
+    k = s1.k
+    e1 = np.ascontiguousarray(s1.entries)
+    e2 = np.ascontiguousarray(s2.entries)
+    out = np.zeros(max(k, 1), dtype=ENTRY)
+    nout, mout = ctypes.c_uint32(), ctypes.c_uint64()
+    rc = _load().oracle_combine(_ptr(e1), len(e1), s1.m, _ptr(e2), len(e2), s2.m, k, _ptr(out),
+                                ctypes.byref(nout), ctypes.byref(mout))
+    if rc != 0:
+        raise RuntimeError("oracle_combine: %d" % rc)
+    return Summary(k, out[: nout.value].copy(), mout.value, s1.n + s2.n)
+
+
+def chunk_bounds(n: int, chunks: int):
+    lib = _load()
+    return [(int(lib.oracle_chunk_begin(n, chunks, c)), int(lib.oracle_chunk_begin(n, chunks, c + 1)))
+            for c in range(chunks)]
+
+
+def chunk_summaries(items, k: int, chunks: int, which=None):
+    """Space Saving summary of each chunk (or of the chunks listed in which)."""
+    a = _items(items)
+    bounds = chunk_bounds(len(a), chunks)
+    idx = range(chunks) if which is None else which
+    return {c: space_saving(a[bounds[c][0]:bounds[c][1]], k) for c in idx}
+
+
+def tree(summaries, k: int) -> Summary:
+    """Fixed binary COMBINE tree over a list of summaries in chunk order."""
+    count = len(summaries)
+    ent = np.zeros(max(k * count, 1), dtype=ENTRY)
+    size = np.zeros(count, dtype=np.uint32)
+    mins = np.zeros(count, dtype=np.uint64)
+    total = 0
+    for i, s in enumerate(summaries):
+        ent[i * k: i * k + len(s.entries)] = s.entries
+        size[i] = len(s.entries)
+        mins[i] = s.m
+        total += s.n
+    rc = _load().oracle_tree(_ptr(ent), _ptr(size), _ptr(mins), count, k)
+    if rc != 0:
+        raise RuntimeError("oracle_tree: %d" % rc)
+    return Summary(k, ent[: size[0]].copy(), int(mins[0]), total)
+
+
+def summary(items, k: int, chunks: int) -> Summary:
+    """Algorithm 1 up to the reduction: partition, per-chunk summaries, tree."""
+    a = _items(items)
+    out = np.zeros(max(k, 1), dtype=ENTRY)
+    nout, mout = ctypes.c_uint32(), ctypes.c_uint64()
+    rc = _load().oracle_summary(_ptr(a), len(a), k, chunks, _ptr(out), ctypes.byref(nout), ctypes.byref(mout))
+    if rc != 0:
+        raise RuntimeError("oracle_summary: %d" % rc)
+    return Summary(k, out[: nout.value].copy(), mout.value, len(a))
+
+
+def run(items, k: int, chunks: int) -> np.ndarray:
+    """ParallelSpaceSaving: the reported k-majority candidates, canonical order."""
+    a = _items(items)
+    if k < 2 or k > len(a):
+        raise ValueError("need 2 <= k <= n")
+    out = np.zeros(k, dtype=ENTRY)
+    nout = ctypes.c_uint32()
+    rc = _load().oracle_run(_ptr(a), len(a), k, chunks, _ptr(out), ctypes.byref(nout))
+    if rc != 0:
+        raise RuntimeError("oracle_run: %d" % rc)
+    return out[: nout.value].copy()
+
+
+def to_tuples(entries: np.ndarray):
+    return [(int(e["item"]), int(e["count"]), int(e["error"])) for e in entries]

@@ -1,0 +1,186 @@
+"""Seeded synthetic item streams shared by the CPU oracle and the GPU library.
+
+Nothing here computes any part of Space Saving or COMBINE: the module only
+writes uint32 item streams (Zipf with permuted or hashed ids, uniform,
+adversarial) from a counter-based generator, so that the oracle and the GPU
+path read byte-identical inputs.  The generator itself is C
+(``streamgen.c``), built with gcc into ``libstreamgen.so`` beside it.
+
+The paper's streams are Zipf with skew 1.1 and 1.8 and n in the billions
+(Section 4, Table 1); universe, generator and seeds are unstated, so the
+recipes below (``plain``, ``plain_large``, ...) are our stand-ins.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "streamgen.c")
+_LIB = os.path.join(_HERE, "libstreamgen.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile streamgen.c into libstreamgen.so (host code, gcc)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-pthread", _SRC, "-o", tmp, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        u64 = ctypes.c_uint64
+        lib.wl_draw.restype = u64
+        lib.wl_draw.argtypes = [u64, u64]
+        lib.wl_fmix32.restype = ctypes.c_uint32
+        lib.wl_fmix32.argtypes = [ctypes.c_uint32]
+        lib.wl_permutation.argtypes = [u32p, ctypes.c_uint32, u64]
+        lib.wl_zipf_perm.argtypes = [u32p, u64, ctypes.c_double, ctypes.c_uint32, u64, u64, ctypes.c_int]
+        lib.wl_zipf_hashed.argtypes = [u32p, u64, ctypes.c_double, u64, u64, ctypes.c_uint32, ctypes.c_int]
+        lib.wl_uniform.argtypes = [u32p, u64, u64, ctypes.c_int]
+        lib.wl_adversarial.argtypes = [u32p, u64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]
+        lib.wl_zipf_ranks.argtypes = [ctypes.POINTER(ctypes.c_uint64), u64, ctypes.c_double, u64, u64]
+        _lib = lib
+    return _lib
+
+
+def _threads(threads: int | None) -> int:
+    if threads is not None:
+        return max(1, int(threads))
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:  # pragma: no cover
+        return max(1, min(16, os.cpu_count() or 1))
+
+
+def _u32ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def draw(key: int, ctr: int) -> int:
+    """The (ctr+1)-th SplitMix64 output for seed ``key`` (64-bit int)."""
+    return int(_load().wl_draw(key & (2**64 - 1), ctr & (2**64 - 1)))
+
+
+def fmix32(h: int) -> int:
+    return int(_load().wl_fmix32(h & 0xFFFFFFFF))
+
+
+def subkey(seed: int, purpose: int) -> int:
+    """Independent 64-bit key for one purpose (ranks, ids, ...) of one seed."""
+    return draw(0x5EED_0000_0000_0000 ^ seed, purpose)
+
+
+def permutation(n_univ: int, key: int) -> np.ndarray:
+    out = np.empty(n_univ, dtype=np.uint32)
+    _load().wl_permutation(_u32ptr(out), n_univ, key)
+    return out
+
+
+def zipf_perm(n: int, alpha: float, n_univ: int, seed: int, threads: int | None = None,
+              out: np.ndarray | None = None) -> np.ndarray:
+    """n items: Zipf(alpha) ranks over 1..n_univ mapped through a seeded permutation."""
+    if n_univ > (1 << 28):
+        raise ValueError("permuted ids need n_univ <= 2^28")
+    out = np.empty(n, dtype=np.uint32) if out is None else out
+    rc = _load().wl_zipf_perm(_u32ptr(out), n, alpha, n_univ, subkey(seed, 1), subkey(seed, 2),
+                              _threads(threads))
+    if rc != 0:
+        raise RuntimeError("wl_zipf_perm failed: %d" % rc)
+    return out
+
+
+def zipf_hashed(n: int, alpha: float, n_univ: int, seed: int, threads: int | None = None,
+                out: np.ndarray | None = None) -> np.ndarray:
+    """n items: Zipf(alpha) ranks over 1..n_univ (<= 2^32), id = fmix32((r-1) ^ key)."""
+    out = np.empty(n, dtype=np.uint32) if out is None else out
+    rc = _load().wl_zipf_hashed(_u32ptr(out), n, alpha, n_univ, subkey(seed, 1),
+                                subkey(seed, 3) & 0xFFFFFFFF, _threads(threads))
+    if rc != 0:
+        raise RuntimeError("wl_zipf_hashed failed: %d" % rc)
+    return out
+
+
+def uniform(n: int, seed: int, threads: int | None = None, out: np.ndarray | None = None) -> np.ndarray:
+    out = np.empty(n, dtype=np.uint32) if out is None else out
+    _load().wl_uniform(_u32ptr(out), n, subkey(seed, 4), _threads(threads))
+    return out
+
+
+def adversarial(n: int, seed: int, d: int = 1 << 20, threads: int | None = None,
+                out: np.ndarray | None = None) -> np.ndarray:
+    """Round-robin over d hashed ids, planted id at positions i % 20 == 19 (5%)."""
+    out = np.empty(n, dtype=np.uint32) if out is None else out
+    _load().wl_adversarial(_u32ptr(out), n, d, subkey(seed, 3) & 0xFFFFFFFF, _threads(threads))
+    return out
+
+
+def adversarial_planted_id(seed: int, d: int = 1 << 20) -> int:
+    return fmix32(d ^ (subkey(seed, 3) & 0xFFFFFFFF))
+
+
+def zipf_ranks(n: int, alpha: float, n_univ: int, key: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.uint64)
+    _load().wl_zipf_ranks(out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n, alpha, n_univ, key)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Workload recipes (shapes of the paper's experiments)
+# ----------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Stream:
+    name: str
+    kind: str          # "zipf_perm" | "zipf_hashed" | "uniform" | "adversarial"
+    n: int
+    alpha: float = 0.0
+    n_univ: int = 0
+    seed: int = 1
+
+    def generate(self, threads: int | None = None, out: np.ndarray | None = None) -> np.ndarray:
+        if self.kind == "zipf_perm":
+            return zipf_perm(self.n, self.alpha, self.n_univ, self.seed, threads, out)
+        if self.kind == "zipf_hashed":
+            return zipf_hashed(self.n, self.alpha, self.n_univ, self.seed, threads, out)
+        if self.kind == "uniform":
+            return uniform(self.n, self.seed, threads, out)
+        if self.kind == "adversarial":
+            return adversarial(self.n, self.seed, threads=threads, out=out)
+        raise ValueError(self.kind)
+
+
+def plain(seed: int = 1, n: int = 1 << 20) -> Stream:
+    """Small plain case: Zipf 1.5 over 2^20 permuted ids (k=100, 64 chunks)."""
+    return Stream("plain_zipf1.5", "zipf_perm", n, 1.5, 1 << 20, seed)
+
+
+def plain_large(alpha: float, seed: int = 1, n: int = 1 << 30) -> Stream:
+    """Large plain case: Zipf alpha over 2^32 hashed ids (k in {500, 2000})."""
+    return Stream("plain_large_zipf%g" % alpha, "zipf_hashed", n, alpha, 1 << 32, seed)
+
+
+def plain_large_uniform(seed: int = 1, n: int = 1 << 30) -> Stream:
+    return Stream("plain_large_uniform", "uniform", n, 0.0, 1 << 32, seed)
+
+
+def plain_highk(seed: int = 1, n: int = 1 << 31) -> Stream:
+    return Stream("plain_highk_zipf1.1", "zipf_hashed", n, 1.1, 1 << 32, seed)
+
+
+def plain_highk_adversarial(seed: int = 1, n: int = 1 << 31) -> Stream:
+    return Stream("plain_highk_adversarial", "adversarial", n, 0.0, 1 << 32, seed)

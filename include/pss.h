@@ -1,0 +1,143 @@
+/*
+ * libpss -- Parallel Space Saving for the k-majority problem on one MI355X.
+ *
+ * The method is that of Cafaro, Pulimeno, Epicoco and Aloisio, "Parallel
+ * Space Saving on Multi and Many-Core Processors" (arXiv 1606.04669):
+ *   - the input array A of n items is cut into C contiguous blocks
+ *     (Section 3, block distribution; Algorithm 1, bounds of the sub-array);
+ *   - each block is summarised by sequential Space Saving with k counters
+ *     (Section 3, second paragraph);
+ *   - the block summaries are merged by COMBINE with Prune(k) (Algorithm 2)
+ *     in a reduction (Algorithm 1, ParallelReduction);
+ *   - the result is pruned to the items above the k-majority threshold
+ *     (Algorithm 1, Pruned; Section 3: f >= floor(n/k) + 1).
+ *
+ * Conventions fixed by this library (the paper leaves them open):
+ *   - items are uint32; every value, 0 and 0xFFFFFFFF included, is an item;
+ *   - eviction takes the counter with the minimum count and, among those, the
+ *     smallest item id; the new item gets count m+1 and error m;
+ *   - a summary with fewer than k used counters has minimum m = 0;
+ *   - COMBINE adds errors like counts; Prune(k) keeps the first k entries in
+ *     the order (count descending, error ascending, item ascending), which is
+ *     also the order of every result this library returns;
+ *   - the reduction is a fixed binary tree over block index: at each level
+ *     summaries 2j and 2j+1 are combined and an odd last one is promoted;
+ *   - block c covers [floor(c*n/C), floor((c+1)*n/C)); C changes results and
+ *     is reported back so that a CPU replay can reproduce them;
+ *   - an item is reported iff count * k > N, where N is the stream length the
+ *     summary covers.
+ *
+ * Memory: pointers named d_* are device pointers (HIP device memory, e.g. a
+ * torch tensor's data_ptr()), owned by the caller and required to stay valid
+ * until the work queued on `stream` has finished.  Pointers named h_* are
+ * host pointers owned by the caller.  Contexts and summaries own their device
+ * memory.  `stream` is a hipStream_t (NULL = the null stream).
+ *
+ * Errors: every int-returning function returns PSS_OK (0) or a negative
+ * PSS_E* code and never throws.  A failed call leaves summaries unchanged.
+ * Handles are not thread-safe: serialise calls on one summary or context.
+ */
+#ifndef PSS_H
+#define PSS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One reported entry (24 bytes, host memory). */
+typedef struct {
+    uint32_t item;     /* the item id */
+    uint32_t reserved; /* always 0 */
+    uint64_t count;    /* estimated frequency f^ (>= true frequency) */
+    uint64_t error;    /* error bound e: count - error <= true frequency */
+} pss_entry;
+
+typedef struct pss_ctx pss_ctx;         /* one HIP device, workspace, tuning */
+typedef struct pss_summary pss_summary; /* one device-resident summary of k counters */
+
+enum {
+    PSS_OK = 0,
+    PSS_EINVAL = -1,  /* null handle/pointer, k < 2, kind unknown, k mismatch */
+    PSS_ERANGE = -2,  /* size outside what the call supports (e.g. k > n in pss_run) */
+    PSS_ENOMEM = -3,  /* device or host allocation failed */
+    PSS_EBUSY = -4,   /* resource limit reached; retry later */
+    PSS_ETRUNC = -5,  /* h_out too small: *n_out holds the required count */
+    PSS_EDEVICE = -6  /* a HIP runtime call or kernel launch failed */
+};
+
+enum {
+    PSS_Q_MAJORITY = 0, /* entries with count * k > N, canonical order */
+    PSS_Q_TOPK = 1      /* the first `cap` entries in canonical order */
+};
+
+/* Largest k the in-LDS kernels accept for this context (device dependent). */
+uint32_t pss_max_k(const pss_ctx* ctx);
+
+/* Create a context on HIP device `device`.  *out receives the handle.
+ * Returns PSS_EINVAL (bad device / null out), PSS_EDEVICE or PSS_ENOMEM. */
+int pss_ctx_create(int device, pss_ctx** out);
+
+/* Release a context and its workspace.  Summaries created from it must be
+ * destroyed first.  NULL is accepted. */
+void pss_ctx_destroy(pss_ctx* ctx);
+
+/* Chunk count the library picks for n items and k counters when a call is
+ * given chunks = 0 (a deterministic function of n, k and the device). */
+uint32_t pss_plan_chunks(const pss_ctx* ctx, uint64_t n, uint32_t k);
+
+/* Create an empty summary with k counters (2 <= k <= pss_max_k()).
+ * Empty means N = 0 and no monitored items: the identity of COMBINE. */
+int pss_create(pss_ctx* ctx, uint32_t k, pss_summary** out);
+
+/* Release a summary (after the work queued on it has finished).  NULL is
+ * accepted. */
+void pss_destroy(pss_summary* s);
+
+/* Append n items (device array d_items, n < 2^32) to summary s:
+ *   B = fixed-tree COMBINE of the Space Saving summaries of C blocks of
+ *       d_items (Algorithm 1 up to the reduction), then S <- COMBINE(S, B)
+ *       and N <- N + n.
+ * chunks = C (0: pss_plan_chunks).  *chunks_used (may be NULL) receives C.
+ * Asynchronous on `stream`.  n = 0 is a no-op. */
+int pss_update(pss_summary* s, const uint32_t* d_items, uint64_t n, uint32_t chunks, void* stream,
+               uint32_t* chunks_used);
+
+/* dst <- COMBINE(dst, src) (Algorithm 2), N(dst) <- N(dst) + N(src).
+ * Both summaries must have the same k (else PSS_EINVAL).  Asynchronous. */
+int pss_merge(pss_summary* dst, const pss_summary* src, void* stream);
+
+/* Query a summary; blocks until the result is on the host.
+ * kind PSS_Q_MAJORITY: the entries with count * k > N (Algorithm 1, Pruned);
+ *      if more than cap qualify, returns PSS_ETRUNC with *n_out = required.
+ * kind PSS_Q_TOPK: the first min(cap, size) entries.
+ * Entries are in canonical order.  *stream_len (may be NULL) receives N. */
+int pss_query(const pss_summary* s, int kind, pss_entry* h_out, uint32_t cap, uint32_t* n_out,
+              uint64_t* stream_len, void* stream);
+
+/* ParallelSpaceSaving(A, n, C, k) (Algorithm 1) in one call: the k-majority
+ * candidates of the device array d_items[0, n), written to h_out (cap
+ * entries) in canonical order, *n_out = number reported.  Requires
+ * 2 <= k <= n (PSS_ERANGE otherwise).  chunks = 0 picks C; *chunks_used (may
+ * be NULL) receives it.  Blocks until the result is on the host. */
+int pss_run(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks,
+            pss_entry* h_out, uint32_t cap, uint32_t* n_out, uint32_t* chunks_used, void* stream);
+
+/* Inspection of the first step: runs the block summaries of d_items[0, n)
+ * for C = chunks blocks (same kernel launch as pss_update) and copies the
+ * summaries of the nsel blocks listed in h_sel to the host: block h_sel[i]
+ * goes to h_out[i*k ...] (unordered entries), its size to h_sizes[i] and its
+ * minimum (0 when not full) to h_mins[i].  Blocks until done. */
+int pss_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks,
+                        const uint32_t* h_sel, uint32_t nsel, pss_entry* h_out, uint32_t* h_sizes,
+                        uint64_t* h_mins, void* stream);
+
+/* Static description of an error code. */
+const char* pss_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSS_H */

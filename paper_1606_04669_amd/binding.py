@@ -1,0 +1,215 @@
+"""ctypes binding of libpss (include/pss.h): argument marshalling only.
+
+Device buffers and streams come from PyTorch (ROCm): ``d_items`` is a
+contiguous int32/uint32 tensor on a HIP device, ``stream`` a
+``torch.cuda.Stream`` (default: the current stream).  Every step of the path
+runs in the library's HIP kernels; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  -- load torch's HIP runtime before libpss binds to one
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpss.so")
+
+PSS_OK, PSS_EINVAL, PSS_ERANGE, PSS_ENOMEM, PSS_EBUSY, PSS_ETRUNC, PSS_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+PSS_Q_MAJORITY, PSS_Q_TOPK = 0, 1
+
+# pss_entry: item u32, reserved u32, count u64, error u64 (24 bytes)
+ENTRY_DTYPE = np.dtype([("item", "<u4"), ("reserved", "<u4"), ("count", "<u8"), ("error", "<u8")])
+
+
+class PssError(RuntimeError):
+    def __init__(self, code: int, what: str, required: int | None = None):
+        self.code = code
+        self.required = required
+        super().__init__("%s: %s (%d)" % (what, strerror(code), code))
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpss.so is not built: run __graft_entry__.build() (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        u32p, u64p = ctypes.POINTER(u32), ctypes.POINTER(u64)
+        L.pss_strerror.restype = ctypes.c_char_p
+        L.pss_strerror.argtypes = [i32]
+        L.pss_ctx_create.argtypes = [i32, ctypes.POINTER(vp)]
+        L.pss_ctx_destroy.argtypes = [vp]
+        L.pss_ctx_destroy.restype = None
+        L.pss_max_k.restype = u32
+        L.pss_max_k.argtypes = [vp]
+        L.pss_plan_chunks.restype = u32
+        L.pss_plan_chunks.argtypes = [vp, u64, u32]
+        L.pss_create.argtypes = [vp, u32, ctypes.POINTER(vp)]
+        L.pss_destroy.argtypes = [vp]
+        L.pss_destroy.restype = None
+        L.pss_update.argtypes = [vp, vp, u64, u32, vp, u32p]
+        L.pss_merge.argtypes = [vp, vp, vp]
+        L.pss_query.argtypes = [vp, i32, vp, u32, u32p, u64p, vp]
+        L.pss_run.argtypes = [vp, vp, u64, u32, u32, vp, u32, u32p, u32p, vp]
+        L.pss_block_summaries.argtypes = [vp, vp, u64, u32, u32, u32p, u32, vp, u32p, u64p, vp]
+        for f in ("pss_ctx_create", "pss_create", "pss_update", "pss_merge", "pss_query", "pss_run",
+                  "pss_block_summaries"):
+            getattr(L, f).restype = i32
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().pss_strerror(code).decode()
+
+
+def _check(rc: int, what: str, required: int | None = None):
+    if rc != PSS_OK:
+        raise PssError(rc, what, required)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _items(d_items):
+    if not isinstance(d_items, torch.Tensor):
+        raise TypeError("d_items must be a torch tensor on a HIP device")
+    if d_items.dtype not in (torch.int32, torch.uint32):
+        raise TypeError("d_items must hold 32-bit items (int32 or uint32)")
+    if not d_items.is_cuda or not d_items.is_contiguous():
+        raise ValueError("d_items must be a contiguous device tensor")
+    return ctypes.c_void_p(d_items.data_ptr()), d_items.numel()
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().pss_ctx_create(device, ctypes.byref(h)), "pss_ctx_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().pss_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def max_k(self) -> int:
+        return int(lib().pss_max_k(self.handle))
+
+    def plan_chunks(self, n: int, k: int) -> int:
+        return int(lib().pss_plan_chunks(self.handle, n, k))
+
+
+def pss_ctx_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def pss_ctx_destroy(ctx: Context):
+    ctx.close()
+
+
+class Summary:
+    def __init__(self, ctx: Context, k: int):
+        h = ctypes.c_void_p()
+        _check(lib().pss_create(ctx.handle, k, ctypes.byref(h)), "pss_create")
+        self.handle = h
+        self.ctx = ctx
+        self.k = k
+
+    def close(self):
+        if self.handle:
+            lib().pss_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pss_create(ctx: Context, k: int) -> Summary:
+    return Summary(ctx, k)
+
+
+def pss_destroy(s: Summary):
+    s.close()
+
+
+def pss_update(s: Summary, d_items, chunks: int = 0, stream=None, n: int | None = None) -> int:
+    """Append d_items[:n] to s; returns the chunk count used."""
+    ptr, numel = _items(d_items)
+    n = numel if n is None else n
+    used = ctypes.c_uint32()
+    _check(lib().pss_update(s.handle, ptr, n, chunks, ctypes.c_void_p(_stream(stream)), ctypes.byref(used)),
+           "pss_update")
+    return int(used.value)
+
+
+def pss_merge(dst: Summary, src: Summary, stream=None):
+    _check(lib().pss_merge(dst.handle, src.handle, ctypes.c_void_p(_stream(stream))), "pss_merge")
+
+
+def pss_query(s: Summary, kind: int = PSS_Q_MAJORITY, cap: int | None = None, stream=None):
+    """Returns (entries as a numpy ENTRY_DTYPE array, stream length N)."""
+    cap = s.k if cap is None else cap
+    out = np.zeros(max(cap, 1), dtype=ENTRY_DTYPE)
+    nout, slen = ctypes.c_uint32(), ctypes.c_uint64()
+    rc = lib().pss_query(s.handle, kind, out.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(nout),
+                         ctypes.byref(slen), ctypes.c_void_p(_stream(stream)))
+    _check(rc, "pss_query", int(nout.value))
+    return out[: min(int(nout.value), cap)].copy(), int(slen.value)
+
+
+def pss_run(ctx: Context, d_items, k: int, chunks: int = 0, cap: int | None = None, stream=None,
+            n: int | None = None):
+    """Algorithm 1 in one call: (reported entries, chunk count used)."""
+    ptr, numel = _items(d_items)
+    n = numel if n is None else n
+    cap = k if cap is None else cap
+    out = np.zeros(max(cap, 1), dtype=ENTRY_DTYPE)
+    nout, used = ctypes.c_uint32(), ctypes.c_uint32()
+    rc = lib().pss_run(ctx.handle, ptr, n, k, chunks, out.ctypes.data_as(ctypes.c_void_p), cap,
+                       ctypes.byref(nout), ctypes.byref(used), ctypes.c_void_p(_stream(stream)))
+    _check(rc, "pss_run", int(nout.value))
+    return out[: int(nout.value)].copy(), int(used.value)
+
+
+def pss_block_summaries(ctx: Context, d_items, k: int, chunks: int, sel, stream=None, n: int | None = None):
+    """Summaries of the blocks listed in sel: list of (entries, minimum)."""
+    ptr, numel = _items(d_items)
+    n = numel if n is None else n
+    sel = np.ascontiguousarray(np.asarray(sel, dtype=np.uint32))
+    out = np.zeros(max(len(sel) * k, 1), dtype=ENTRY_DTYPE)
+    sizes = np.zeros(max(len(sel), 1), dtype=np.uint32)
+    mins = np.zeros(max(len(sel), 1), dtype=np.uint64)
+    rc = lib().pss_block_summaries(ctx.handle, ptr, n, k, chunks,
+                                   sel.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), len(sel),
+                                   out.ctypes.data_as(ctypes.c_void_p),
+                                   sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                   mins.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                   ctypes.c_void_p(_stream(stream)))
+    _check(rc, "pss_block_summaries")
+    return [(out[i * k: i * k + int(sizes[i])].copy(), int(mins[i])) for i in range(len(sel))]
+
+
+def to_tuples(entries):
+    return [(int(e["item"]), int(e["count"]), int(e["error"])) for e in entries]

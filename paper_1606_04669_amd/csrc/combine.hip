@@ -1,0 +1,278 @@
+// COMBINE with Prune(k) (Algorithm 2) and the fixed binary reduction tree
+// (Algorithm 1, ParallelReduction).  One workgroup merges one pair.
+//
+// Candidates of S_C live in LDS: S2's entries are staged first (count and
+// error raised by m1, as for items only in S2), then every S1 entry looks its
+// item up in a hash of S2: a shared item adds both estimates and retires the
+// staged S2 entry; an item only in S1 is raised by m2.  Prune(k) keeps the k
+// best candidates in the order (count desc, error asc, item asc): the k-th
+// best key is found by a most-significant-digit radix select over the
+// composite key U = (~count, error, item), smaller U = better, and every
+// candidate with U at most that key is kept.  Items are unique in a summary,
+// so U is a total order and the kept set is exactly the first k.
+#include "pss_device.h"
+#include "pss_layout.h"
+#include "pss_kernels.h"
+
+namespace pss {
+
+constexpr uint32_t kCombineThreads = 256;
+constexpr uint8_t kAlive = 1, kCand = 2;
+
+template <typename CO>
+struct CombineLds {
+    uint32_t cap;   // candidate capacity (2k)
+    uint32_t hsize; // S2 hash slots
+    uint32_t off_cc, off_ce, off_ci, off_flag, off_hash, off_hist, off_misc, bytes;
+
+    __host__ __device__ static CombineLds make(uint32_t k) {
+        CombineLds L;
+        L.cap = 2 * k;
+        L.hsize = next_pow2(2 * k);
+        if (L.hsize < 64) L.hsize = 64;
+        uint32_t o = 0;
+        L.off_cc = o;   o += sizeof(CO) * L.cap;
+        L.off_ce = o;   o += sizeof(CO) * L.cap;
+        L.off_ci = o;   o += 4 * L.cap;
+        L.off_flag = o; o += (L.cap + 15) & ~15u;
+        L.off_hash = o; o += 4 * L.hsize;
+        L.off_hist = o; o += 4 * 256;
+        L.off_misc = o; o += 64;
+        L.bytes = o;
+        return L;
+    }
+};
+
+template <typename CO>
+__device__ __forceinline__ uint32_t key_digit(CO c, CO e, uint32_t it, uint32_t p) {
+    constexpr uint32_t W = sizeof(CO);
+    if (p < W) return (uint32_t)((~c) >> (8 * (W - 1 - p))) & 255u;
+    if (p < 2 * W) return (uint32_t)(e >> (8 * (2 * W - 1 - p))) & 255u;
+    return (it >> (8 * (2 * W + 3 - p))) & 255u;
+}
+
+// a strictly better than b in the canonical order
+template <typename CO>
+__device__ __forceinline__ bool better(CO ca, CO ea, uint32_t ia, CO cb, CO eb, uint32_t ib) {
+    if (ca != cb) return ca > cb;
+    if (ea != eb) return ea < eb;
+    return ia < ib;
+}
+
+template <typename C1, typename C2, typename CO>
+__device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uint32_t n1, C1 m1_,
+                             const uint32_t* i2, const C2* c2, const C2* e2, uint32_t n2, C2 m2_, uint32_t k,
+                             uint32_t* io, CO* co, CO* eo, uint32_t* osize, CO* omin, unsigned char* smem) {
+    const CombineLds<CO> L = CombineLds<CO>::make(k);
+    CO* cc = (CO*)(smem + L.off_cc);
+    CO* ce = (CO*)(smem + L.off_ce);
+    uint32_t* ci = (uint32_t*)(smem + L.off_ci);
+    uint8_t* flag = (uint8_t*)(smem + L.off_flag);
+    uint32_t* hash = (uint32_t*)(smem + L.off_hash);
+    uint32_t* hist = (uint32_t*)(smem + L.off_hist);
+    uint32_t* misc = (uint32_t*)(smem + L.off_misc);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t hbits = log2_pow2(L.hsize);
+    const uint32_t hmask = L.hsize - 1;
+    const CO m1 = (CO)m1_, m2 = (CO)m2_;
+    const uint32_t nc = n1 + n2;
+
+    // stage S2 as candidates [n1, n1 + n2): items only in S2 get + m1
+    for (uint32_t j = tid; j < n2; j += kCombineThreads) {
+        ci[n1 + j] = i2[j];
+        cc[n1 + j] = (CO)c2[j] + m1;
+        ce[n1 + j] = (CO)e2[j] + m1;
+        flag[n1 + j] = kAlive;
+    }
+    for (uint32_t h = tid; h < L.hsize; h += kCombineThreads) hash[h] = 0u;
+    __syncthreads();
+    for (uint32_t j = tid; j < n2; j += kCombineThreads) {
+        uint32_t h = hash_slot(ci[n1 + j], hbits);
+        while (atomicCAS(&hash[h], 0u, j + 1u) != 0u) h = (h + 1) & hmask;
+    }
+    __syncthreads();
+    // S1 entries: Find in S2, add both estimates (and retire S2's), or + m2
+    for (uint32_t i = tid; i < n1; i += kCombineThreads) {
+        const uint32_t x = i1[i];
+        uint32_t h = hash_slot(x, hbits);
+        int32_t found = -1;
+        for (;;) {
+            uint32_t v = hash[h];
+            if (v == 0u) break;
+            if (ci[n1 + v - 1] == x) {
+                found = (int32_t)(v - 1);
+                break;
+            }
+            h = (h + 1) & hmask;
+        }
+        CO c = (CO)c1[i], e = (CO)e1[i];
+        if (found >= 0) {
+            c += cc[n1 + found] - m1;
+            e += ce[n1 + found] - m1;
+            flag[n1 + found] = 0;
+        } else {
+            c += m2;
+            e += m2;
+        }
+        ci[i] = x;
+        cc[i] = c;
+        ce[i] = e;
+        flag[i] = kAlive;
+    }
+    __syncthreads();
+
+    // number of distinct candidates
+    uint32_t live = 0;
+    for (uint32_t i = tid; i < nc; i += kCombineThreads) live += flag[i] & kAlive;
+    if (tid < 4) misc[tid] = 0;
+    __syncthreads();
+    live = wave_sum_u32(live);
+    if (lane_id() == 0) atomicAdd(&misc[0], live);
+    __syncthreads();
+    const uint32_t ns = misc[0];
+    __syncthreads();
+
+    // Prune(k): radix select of the k-th best key when there are more than k
+    int32_t star = -1;  // index of the worst kept candidate
+    if (ns > k) {
+        for (uint32_t i = tid; i < nc; i += kCombineThreads) flag[i] = (flag[i] & kAlive) ? (kAlive | kCand) : 0;
+        uint32_t rank = k - 1;
+        constexpr uint32_t NB = 2 * sizeof(CO) + 4;
+        for (uint32_t p = 0; p < NB; ++p) {
+            hist[tid] = 0u;
+            __syncthreads();
+            for (uint32_t i = tid; i < nc; i += kCombineThreads)
+                if (flag[i] & kCand) atomicAdd(&hist[key_digit<CO>(cc[i], ce[i], ci[i], p)], 1u);
+            __syncthreads();
+            if (tid < kWave) {
+                // bucket holding the rank-th candidate: 4 bins per lane, then a wave scan
+                uint32_t b0 = hist[4 * tid], b1 = hist[4 * tid + 1], b2 = hist[4 * tid + 2], b3 = hist[4 * tid + 3];
+                uint32_t s = b0 + b1 + b2 + b3, incl = s;
+                for (int off = 1; off < 64; off <<= 1) {
+                    uint32_t t = (uint32_t)__shfl_up((int)incl, off);
+                    if ((int)tid >= off) incl += t;
+                }
+                uint32_t excl = incl - s;
+                bool here = excl <= rank && rank < incl;
+                if (here) {
+                    uint32_t rr = rank - excl, bin = 4 * tid;
+                    if (rr >= b0) { rr -= b0; ++bin;
+                        if (rr >= b1) { rr -= b1; ++bin;
+                            if (rr >= b2) { rr -= b2; ++bin; } } }
+                    misc[1] = bin;
+                    misc[2] = rr;
+                }
+            }
+            __syncthreads();
+            const uint32_t sel = misc[1];
+            rank = misc[2];
+            for (uint32_t i = tid; i < nc; i += kCombineThreads)
+                if ((flag[i] & kCand) && key_digit<CO>(cc[i], ce[i], ci[i], p) != sel) flag[i] &= (uint8_t)~kCand;
+            __syncthreads();
+        }
+        for (uint32_t i = tid; i < nc; i += kCombineThreads)
+            if (flag[i] & kCand) misc[3] = i;
+        __syncthreads();
+        star = (int32_t)misc[3];
+        __syncthreads();
+    }
+
+    // keep = alive and not worse than the k-th best; written in candidate order
+    CO sc = 0, se = 0;
+    uint32_t si = 0;
+    if (star >= 0) {
+        sc = cc[star];
+        se = ce[star];
+        si = ci[star];
+    }
+    if (tid == 0) misc[0] = 0u;
+    __syncthreads();
+    CO local_min = ~(CO)0;
+    for (uint32_t base = 0; base < nc; base += kCombineThreads) {
+        const uint32_t i = base + tid;
+        bool keep = false;
+        if (i < nc && (flag[i] & kAlive)) keep = (star < 0) || !better<CO>(sc, se, si, cc[i], ce[i], ci[i]);
+        const uint64_t bm = ballot(keep);
+        const uint32_t w = tid / kWave;
+        if (lane_id() == 0) hist[w] = popc64(bm);
+        __syncthreads();
+        uint32_t before = misc[0];
+        for (uint32_t q = 0; q < w; ++q) before += hist[q];
+        if (keep) {
+            const uint32_t o = before + mbcnt(bm);
+            io[o] = ci[i];
+            co[o] = cc[i];
+            eo[o] = ce[i];
+            local_min = cc[i] < local_min ? cc[i] : local_min;
+        }
+        __syncthreads();
+        if (tid == 0) misc[0] += hist[0] + hist[1] + hist[2] + hist[3];
+        __syncthreads();
+    }
+    const uint32_t kept = misc[0];
+    // minimum of the result: 0 unless all k counters are used
+    CO wmin = wave_min_u64((uint64_t)local_min);
+    __shared__ uint64_t red[kCombineThreads / kWave];
+    if (lane_id() == 0) red[tid / kWave] = (uint64_t)wmin;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t mn = red[0];
+        for (uint32_t q = 1; q < kCombineThreads / kWave; ++q) mn = red[q] < mn ? red[q] : mn;
+        *osize = kept;
+        *omin = (kept == k) ? (CO)mn : (CO)0;
+    }
+}
+
+__global__ __launch_bounds__(kCombineThreads) void combine_level_kernel(BlockSummaries v, uint32_t k, uint32_t count,
+                                                                        uint32_t step) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint64_t a = 2ull * step * blockIdx.x;
+    const uint64_t b = a + step;
+    if (b >= count) return;
+    combine_node<uint32_t, uint32_t, uint32_t>(v.item + a * k, v.cnt + a * k, v.err + a * k, v.size[a], v.min[a],
+                                               v.item + b * k, v.cnt + b * k, v.err + b * k, v.size[b], v.min[b], k,
+                                               v.item + a * k, v.cnt + a * k, v.err + a * k, &v.size[a], &v.min[a],
+                                               smem);
+}
+
+__global__ __launch_bounds__(kCombineThreads) void fold_kernel(WideSummary d, BlockSummaries s, uint32_t k) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    combine_node<uint64_t, uint32_t, uint64_t>(d.item, d.cnt, d.err, d.size[0], d.min[0], s.item, s.cnt, s.err,
+                                               s.size[0], s.min[0], k, d.item, d.cnt, d.err, d.size, d.min, smem);
+}
+
+__global__ __launch_bounds__(kCombineThreads) void merge_kernel(WideSummary d, WideSummary s, uint32_t k) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    combine_node<uint64_t, uint64_t, uint64_t>(d.item, d.cnt, d.err, d.size[0], d.min[0], s.item, s.cnt, s.err,
+                                               s.size[0], s.min[0], k, d.item, d.cnt, d.err, d.size, d.min, smem);
+}
+
+uint32_t combine_lds_bytes(uint32_t k, bool wide) {
+    return wide ? CombineLds<uint64_t>::make(k).bytes : CombineLds<uint32_t>::make(k).bytes;
+}
+
+hipError_t launch_combine_level(const BlockSummaries& v, uint32_t k, uint32_t count, uint32_t step,
+                                hipStream_t stream) {
+    if (step >= count) return hipSuccess;
+    const uint32_t pairs = (count - step + 2 * step - 1) / (2 * step);
+    const uint32_t lds = CombineLds<uint32_t>::make(k).bytes;
+    hipFuncSetAttribute((const void*)combine_level_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(combine_level_kernel, dim3(pairs), dim3(kCombineThreads), lds, stream, v, k, count, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(const WideSummary& dst, const BlockSummaries& src, uint32_t k, hipStream_t stream) {
+    const uint32_t lds = CombineLds<uint64_t>::make(k).bytes;
+    hipFuncSetAttribute((const void*)fold_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(kCombineThreads), lds, stream, dst, src, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(const WideSummary& dst, const WideSummary& src, uint32_t k, hipStream_t stream) {
+    const uint32_t lds = CombineLds<uint64_t>::make(k).bytes;
+    hipFuncSetAttribute((const void*)merge_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(merge_kernel, dim3(1), dim3(kCombineThreads), lds, stream, dst, src, k);
+    return hipGetLastError();
+}
+
+}  // namespace pss

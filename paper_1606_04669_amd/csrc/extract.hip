@@ -1,0 +1,117 @@
+// Report step (Algorithm 1, Pruned): the entries of a summary above the
+// k-majority threshold, count * k > N (Section 3: f >= floor(N/k) + 1), or the
+// first `cap` entries, in the canonical order (count desc, error asc, item
+// asc).  One workgroup sorts the <= k entries in LDS with a bitonic network.
+#include "pss_device.h"
+#include "pss_layout.h"
+#include "pss_kernels.h"
+
+namespace pss {
+
+constexpr uint32_t kExtractThreads = 1024;
+
+__host__ __device__ inline uint32_t extract_cap(uint32_t k) {
+    uint32_t P = next_pow2(k);
+    return P < 2 ? 2 : P;
+}
+
+uint32_t extract_lds_bytes(uint32_t k) { return extract_cap(k) * (8 + 8 + 4); }
+
+__device__ __forceinline__ bool ext_better(uint64_t ca, uint64_t ea, uint32_t ia, uint64_t cb, uint64_t eb,
+                                           uint32_t ib) {
+    if (ca != cb) return ca > cb;
+    if (ea != eb) return ea < eb;
+    return ia < ib;
+}
+
+__global__ __launch_bounds__(kExtractThreads) void extract_kernel(WideSummary s, uint32_t k, uint64_t N, int kind,
+                                                                  uint32_t cap, DevEntry* out, uint32_t* out_count) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t P0 = extract_cap(k);
+    uint64_t* cc = (uint64_t*)smem;
+    uint64_t* ce = cc + P0;
+    uint32_t* ci = (uint32_t*)(ce + P0);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t size = s.size[0];
+    uint32_t P = next_pow2(size);
+    if (P < 2) P = 2;
+    for (uint32_t i = tid; i < P; i += kExtractThreads) {
+        if (i < size) {
+            cc[i] = s.cnt[i];
+            ce[i] = s.err[i];
+            ci[i] = s.item[i];
+        } else {  // padding sorts after every real entry (real counts are >= 1)
+            cc[i] = 0;
+            ce[i] = ~0ull;
+            ci[i] = 0xFFFFFFFFu;
+        }
+    }
+    __syncthreads();
+    for (uint32_t w = 2; w <= P; w <<= 1) {
+        for (uint32_t stride = w >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t t = tid; t < P / 2; t += kExtractThreads) {
+                uint32_t i = 2 * t - (t & (stride - 1));
+                uint32_t j = i + stride;
+                bool up = (i & w) == 0;
+                bool jb = ext_better(cc[j], ce[j], ci[j], cc[i], ce[i], ci[i]);
+                if (jb == up) {
+                    uint64_t tc = cc[i], te = ce[i];
+                    uint32_t ti = ci[i];
+                    cc[i] = cc[j]; ce[i] = ce[j]; ci[i] = ci[j];
+                    cc[j] = tc; ce[j] = te; ci[j] = ti;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    uint32_t q;
+    if (kind == 0) {
+        // reported prefix: count > floor(N / k)
+        const uint64_t thr = N / k;
+        __shared__ uint32_t qs;
+        if (tid == 0) qs = 0;
+        __syncthreads();
+        for (uint32_t i = tid; i < size; i += kExtractThreads) {
+            bool in = cc[i] > thr;
+            bool next_out = (i + 1 >= size) || !(cc[i + 1] > thr);
+            if (in && next_out) qs = i + 1;
+        }
+        __syncthreads();
+        q = qs;
+    } else {
+        q = size < cap ? size : cap;
+    }
+    const uint32_t wn = q < cap ? q : cap;
+    for (uint32_t i = tid; i < wn; i += kExtractThreads) {
+        DevEntry e;
+        e.item = ci[i];
+        e.reserved = 0;
+        e.count = cc[i];
+        e.error = ce[i];
+        out[i] = e;
+    }
+    if (tid == 0) *out_count = q;
+}
+
+hipError_t launch_extract(const WideSummary& s, uint32_t k, uint64_t N, int kind, uint32_t cap, DevEntry* out,
+                          uint32_t* out_count, hipStream_t stream) {
+    const uint32_t lds = extract_lds_bytes(k);
+    hipFuncSetAttribute((const void*)extract_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(extract_kernel, dim3(1), dim3(kExtractThreads), lds, stream, s, k, N, kind, cap, out,
+                       out_count);
+    return hipGetLastError();
+}
+
+__global__ void reset_kernel(WideSummary s) {
+    if (threadIdx.x == 0) {
+        s.size[0] = 0;
+        s.min[0] = 0;
+    }
+}
+
+hipError_t launch_reset(const WideSummary& s, hipStream_t stream) {
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, stream, s);
+    return hipGetLastError();
+}
+
+}  // namespace pss

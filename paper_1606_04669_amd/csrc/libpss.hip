@@ -1,0 +1,400 @@
+// C-ABI of libpss: contexts, device-resident summaries, and the launch
+// sequence of the parallel algorithm (Algorithm 1): block summaries, the fixed
+// COMBINE tree, the fold into the live summary, and the report.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string.h>
+
+#include "pss.h"
+#include "pss_kernels.h"
+#include "pss_layout.h"
+
+using namespace pss;
+
+namespace {
+
+constexpr uint32_t kMaxChunks = 1u << 22;
+
+struct DeviceBuffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    int grow(size_t need) {
+        if (need <= bytes) return PSS_OK;
+        void* p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess) return PSS_ENOMEM;
+        if (ptr) hipFree(ptr);
+        ptr = p;
+        bytes = need;
+        return PSS_OK;
+    }
+    void release() {
+        if (ptr) hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct pss_ctx {
+    int device = 0;
+    int cu_count = 0;
+    size_t lds_max = 0;      // dynamic LDS per workgroup
+    size_t lds_per_cu = 0;
+    DeviceBuffer blocks;     // block summaries of one update
+    DeviceBuffer query;      // report buffer
+    void* pinned = nullptr;  // host staging for reports
+    size_t pinned_bytes = 0;
+    std::map<uint32_t, pss_summary*> run_cache;
+};
+
+struct pss_summary {
+    pss_ctx* ctx = nullptr;
+    uint32_t k = 0;
+    uint64_t n = 0;  // stream length covered
+    void* mem = nullptr;
+    WideSummary view{};
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
+BlockSummaries carve_blocks(void* base, uint32_t chunks, uint32_t k) {
+    BlockSummaries v;
+    size_t per = (size_t)chunks * k * sizeof(uint32_t);
+    char* p = (char*)base;
+    v.item = (uint32_t*)p;
+    p += align_up(per, 256);
+    v.cnt = (uint32_t*)p;
+    p += align_up(per, 256);
+    v.err = (uint32_t*)p;
+    p += align_up(per, 256);
+    v.size = (uint32_t*)p;
+    p += align_up((size_t)chunks * 4, 256);
+    v.min = (uint32_t*)p;
+    return v;
+}
+
+size_t blocks_bytes(uint32_t chunks, uint32_t k) {
+    size_t per = (size_t)chunks * k * sizeof(uint32_t);
+    return 3 * align_up(per, 256) + 2 * align_up((size_t)chunks * 4, 256);
+}
+
+size_t summary_bytes(uint32_t k) {
+    return align_up((size_t)k * 4, 256) + 2 * align_up((size_t)k * 8, 256) + 256 + 256;
+}
+
+WideSummary carve_summary(void* base, uint32_t k) {
+    WideSummary v;
+    char* p = (char*)base;
+    v.item = (uint32_t*)p;
+    p += align_up((size_t)k * 4, 256);
+    v.cnt = (uint64_t*)p;
+    p += align_up((size_t)k * 8, 256);
+    v.err = (uint64_t*)p;
+    p += align_up((size_t)k * 8, 256);
+    v.size = (uint32_t*)p;
+    p += 256;
+    v.min = (uint64_t*)p;
+    return v;
+}
+
+bool k_fits(const pss_ctx* ctx, uint32_t k) {
+    if (k < 2) return false;
+    return chunk_summary_lds_bytes(k) <= ctx->lds_max && combine_lds_bytes(k, true) <= ctx->lds_max &&
+           extract_lds_bytes(k) <= ctx->lds_max;
+}
+
+int check(hipError_t e) { return e == hipSuccess ? PSS_OK : PSS_EDEVICE; }
+
+// block summaries of d_items[0, n) into the context workspace
+int run_blocks(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks, hipStream_t st,
+               BlockSummaries* out) {
+    int rc = ctx->blocks.grow(blocks_bytes(chunks, k));
+    if (rc != PSS_OK) return rc;
+    *out = carve_blocks(ctx->blocks.ptr, chunks, k);
+    return check(launch_chunk_summary(d_items, n, chunks, k, *out, st));
+}
+
+int ensure_pinned(pss_ctx* ctx, size_t bytes) {
+    if (bytes <= ctx->pinned_bytes) return PSS_OK;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return PSS_ENOMEM;
+    if (ctx->pinned) hipHostFree(ctx->pinned);
+    ctx->pinned = p;
+    ctx->pinned_bytes = bytes;
+    return PSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pss_strerror(int code) {
+    switch (code) {
+    case PSS_OK: return "ok";
+    case PSS_EINVAL: return "invalid argument";
+    case PSS_ERANGE: return "size out of supported range";
+    case PSS_ENOMEM: return "out of memory";
+    case PSS_EBUSY: return "resource busy";
+    case PSS_ETRUNC: return "output buffer too small";
+    case PSS_EDEVICE: return "HIP device error";
+    default: return "unknown error";
+    }
+}
+
+int pss_ctx_create(int device, pss_ctx** out) {
+    if (!out) return PSS_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return PSS_EDEVICE;
+    if (device < 0 || device >= ndev) return PSS_EINVAL;
+    pss_ctx* ctx = new (std::nothrow) pss_ctx();
+    if (!ctx) return PSS_ENOMEM;
+    ctx->device = device;
+    DeviceGuard g(device);
+    int cus = 0, lds = 0, ldscu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
+        delete ctx;
+        return PSS_EDEVICE;
+    }
+    if (hipDeviceGetAttribute(&ldscu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) != hipSuccess)
+        ldscu = lds;
+    ctx->cu_count = cus;
+    ctx->lds_max = (size_t)lds;
+    ctx->lds_per_cu = (size_t)(ldscu > 0 ? ldscu : lds);
+    *out = ctx;
+    return PSS_OK;
+}
+
+void pss_ctx_destroy(pss_ctx* ctx) {
+    if (!ctx) return;
+    DeviceGuard g(ctx->device);
+    for (auto& kv : ctx->run_cache) pss_destroy(kv.second);
+    ctx->blocks.release();
+    ctx->query.release();
+    if (ctx->pinned) hipHostFree(ctx->pinned);
+    delete ctx;
+}
+
+uint32_t pss_max_k(const pss_ctx* ctx) {
+    if (!ctx) return 0;
+    uint32_t lo = 2, hi = 1u << 20;
+    if (!k_fits(ctx, lo)) return 0;
+    while (lo < hi) {
+        uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (k_fits(ctx, mid)) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+uint32_t pss_plan_chunks(const pss_ctx* ctx, uint64_t n, uint32_t k) {
+    if (!ctx || n == 0 || k < 2) return 1;
+    // enough resident waves to cover every CU a few times over, while keeping
+    // blocks long next to k (the reduction tree moves ~C*k entries)
+    uint64_t per_cu = ctx->lds_per_cu / std::max<uint32_t>(1, chunk_summary_lds_bytes(k));
+    if (per_cu < 1) per_cu = 1;
+    uint64_t want = (uint64_t)ctx->cu_count * per_cu * 4;
+    uint64_t cap_len = n / (16ull * k);
+    if (cap_len < 1) cap_len = 1;
+    uint64_t c = std::min(want, cap_len);
+    c = std::min<uint64_t>(c, kMaxChunks);
+    return (uint32_t)std::max<uint64_t>(c, 1);
+}
+
+int pss_create(pss_ctx* ctx, uint32_t k, pss_summary** out) {
+    if (!ctx || !out) return PSS_EINVAL;
+    *out = nullptr;
+    if (k < 2) return PSS_EINVAL;
+    if (!k_fits(ctx, k)) return PSS_ERANGE;
+    DeviceGuard g(ctx->device);
+    pss_summary* s = new (std::nothrow) pss_summary();
+    if (!s) return PSS_ENOMEM;
+    s->ctx = ctx;
+    s->k = k;
+    if (hipMalloc(&s->mem, summary_bytes(k)) != hipSuccess) {
+        delete s;
+        return PSS_ENOMEM;
+    }
+    s->view = carve_summary(s->mem, k);
+    if (hipMemset(s->view.size, 0, 256) != hipSuccess || hipMemset(s->view.min, 0, 256) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        hipFree(s->mem);
+        delete s;
+        return PSS_EDEVICE;
+    }
+    *out = s;
+    return PSS_OK;
+}
+
+void pss_destroy(pss_summary* s) {
+    if (!s) return;
+    DeviceGuard g(s->ctx->device);
+    if (s->mem) hipFree(s->mem);
+    delete s;
+}
+
+int pss_update(pss_summary* s, const uint32_t* d_items, uint64_t n, uint32_t chunks, void* stream,
+               uint32_t* chunks_used) {
+    if (!s) return PSS_EINVAL;
+    pss_ctx* ctx = s->ctx;
+    const uint32_t k = s->k;
+    if (n == 0) {
+        if (chunks_used) *chunks_used = chunks;
+        return PSS_OK;
+    }
+    if (!d_items) return PSS_EINVAL;
+    if (n >= (1ull << 32)) return PSS_ERANGE;
+    const uint32_t C = chunks ? chunks : pss_plan_chunks(ctx, n, k);
+    if (C > kMaxChunks) return PSS_ERANGE;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    BlockSummaries b;
+    int rc = run_blocks(ctx, d_items, n, k, C, st, &b);
+    if (rc != PSS_OK) return rc;
+    for (uint32_t step = 1; step < C; step <<= 1) {
+        rc = check(launch_combine_level(b, k, C, step, st));
+        if (rc != PSS_OK) return rc;
+    }
+    rc = check(launch_fold(s->view, b, k, st));
+    if (rc != PSS_OK) return rc;
+    s->n += n;
+    if (chunks_used) *chunks_used = C;
+    return PSS_OK;
+}
+
+int pss_merge(pss_summary* dst, const pss_summary* src, void* stream) {
+    if (!dst || !src || dst == src) return PSS_EINVAL;
+    if (dst->k != src->k || dst->ctx->device != src->ctx->device) return PSS_EINVAL;
+    DeviceGuard g(dst->ctx->device);
+    int rc = check(launch_merge(dst->view, src->view, dst->k, (hipStream_t)stream));
+    if (rc != PSS_OK) return rc;
+    dst->n += src->n;
+    return PSS_OK;
+}
+
+int pss_query(const pss_summary* s, int kind, pss_entry* h_out, uint32_t cap, uint32_t* n_out,
+              uint64_t* stream_len, void* stream) {
+    if (!s || !n_out || (cap > 0 && !h_out)) return PSS_EINVAL;
+    if (kind != PSS_Q_MAJORITY && kind != PSS_Q_TOPK) return PSS_EINVAL;
+    pss_ctx* ctx = s->ctx;
+    const uint32_t k = s->k;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t ebytes = (size_t)k * sizeof(DevEntry);
+    const size_t qbytes = 256 + ebytes;
+    int rc = ctx->query.grow(qbytes);
+    if (rc != PSS_OK) return rc;
+    rc = ensure_pinned(ctx, qbytes);
+    if (rc != PSS_OK) return rc;
+    uint32_t* d_count = (uint32_t*)ctx->query.ptr;
+    DevEntry* d_ent = (DevEntry*)((char*)ctx->query.ptr + 256);
+    const uint32_t dev_cap = kind == PSS_Q_TOPK ? std::min(cap, k) : k;
+    rc = check(launch_extract(s->view, k, s->n, kind, dev_cap, d_ent, d_count, st));
+    if (rc != PSS_OK) return rc;
+    if (hipMemcpyAsync(ctx->pinned, ctx->query.ptr, qbytes, hipMemcpyDeviceToHost, st) != hipSuccess)
+        return PSS_EDEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return PSS_EDEVICE;
+    const uint32_t q = *(const uint32_t*)ctx->pinned;
+    if (stream_len) *stream_len = s->n;
+    *n_out = q;
+    if (kind == PSS_Q_MAJORITY && q > cap) return PSS_ETRUNC;
+    const uint32_t w = std::min(q, cap);
+    if (w) memcpy(h_out, (const char*)ctx->pinned + 256, (size_t)w * sizeof(pss_entry));
+    return PSS_OK;
+}
+
+int pss_run(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks, pss_entry* h_out,
+            uint32_t cap, uint32_t* n_out, uint32_t* chunks_used, void* stream) {
+    if (!ctx || !d_items || !n_out || (cap > 0 && !h_out)) return PSS_EINVAL;
+    if (k < 2 || (uint64_t)k > n) return PSS_ERANGE;
+    if (!k_fits(ctx, k)) return PSS_ERANGE;
+    DeviceGuard g(ctx->device);
+    pss_summary* s = nullptr;
+    try {
+        auto it = ctx->run_cache.find(k);
+        if (it == ctx->run_cache.end()) {
+            int rc = pss_create(ctx, k, &s);
+            if (rc != PSS_OK) return rc;
+            ctx->run_cache[k] = s;
+        } else {
+            s = it->second;
+        }
+    } catch (const std::bad_alloc&) {
+        if (s) pss_destroy(s);
+        return PSS_ENOMEM;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int rc = check(launch_reset(s->view, st));
+    if (rc != PSS_OK) return rc;
+    s->n = 0;
+    rc = pss_update(s, d_items, n, chunks, stream, chunks_used);
+    if (rc != PSS_OK) return rc;
+    return pss_query(s, PSS_Q_MAJORITY, h_out, cap, n_out, nullptr, stream);
+}
+
+int pss_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks,
+                        const uint32_t* h_sel, uint32_t nsel, pss_entry* h_out, uint32_t* h_sizes,
+                        uint64_t* h_mins, void* stream) {
+    if (!ctx || (n > 0 && !d_items) || chunks == 0 || (nsel > 0 && (!h_sel || !h_out || !h_sizes || !h_mins)))
+        return PSS_EINVAL;
+    if (k < 2) return PSS_EINVAL;
+    if (!k_fits(ctx, k) || n >= (1ull << 32) || chunks > kMaxChunks) return PSS_ERANGE;
+    for (uint32_t i = 0; i < nsel; ++i)
+        if (h_sel[i] >= chunks) return PSS_EINVAL;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    BlockSummaries b;
+    int rc = run_blocks(ctx, d_items, n, k, chunks, st, &b);
+    if (rc != PSS_OK) return rc;
+    if (hipStreamSynchronize(st) != hipSuccess) return PSS_EDEVICE;
+    for (uint32_t i = 0; i < nsel; ++i) {
+        const uint32_t c = h_sel[i];
+        uint32_t sz = 0, mn = 0;
+        if (hipMemcpy(&sz, b.size + c, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(&mn, b.min + c, 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return PSS_EDEVICE;
+        if (sz > k) return PSS_EDEVICE;
+        h_sizes[i] = sz;
+        h_mins[i] = mn;
+        if (sz == 0) continue;
+        uint32_t* tmp = new (std::nothrow) uint32_t[3 * (size_t)sz];
+        if (!tmp) return PSS_ENOMEM;
+        const size_t off = (size_t)c * k;
+        if (hipMemcpy(tmp, b.item + off, 4 * (size_t)sz, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(tmp + sz, b.cnt + off, 4 * (size_t)sz, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(tmp + 2 * (size_t)sz, b.err + off, 4 * (size_t)sz, hipMemcpyDeviceToHost) != hipSuccess) {
+            delete[] tmp;
+            return PSS_EDEVICE;
+        }
+        pss_entry* o = h_out + (size_t)i * k;
+        for (uint32_t e = 0; e < sz; ++e) {
+            o[e].item = tmp[e];
+            o[e].reserved = 0;
+            o[e].count = tmp[sz + e];
+            o[e].error = tmp[2 * (size_t)sz + e];
+        }
+        delete[] tmp;
+    }
+    return PSS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput of the Parallel Space Saving hot path on one MI355X.
+
+One step = one pass of the whole path (block summaries -> fixed COMBINE tree
+-> fold -> report, Algorithm 1 with Algorithm 2 as the reduction operator)
+over every case of the workload.  Default workload "plain-large": four
+streams of n = 2^30 uint32 items resident in HBM -- Zipf alpha 0.8, 1.2, 1.8
+over 2^32 hashed ids and a uniform control -- each summarised with k = 500
+and k = 2000 counters, chunk count picked by the library's planner and
+recorded.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload_cases(name: str, n_log2: int, seed: int):
+    import workloads as W
+    n = 1 << n_log2
+    if name == "plain-large":
+        streams = [W.plain_large(0.8, seed, n), W.plain_large(1.2, seed, n), W.plain_large(1.8, seed, n),
+                   W.plain_large_uniform(seed, n)]
+        ks = [500, 2000]
+        return streams, ks
+    if name == "plain":
+        return [W.plain(seed, n)], [100]
+    raise SystemExit("unknown workload %s" % name)
+
+
+def cpu_baseline(streams, ks, host, chunks_of, sample_log2: int):
+    """The oracle, single-threaded, on the first 2^sample_log2 items of every case."""
+    import oracle
+    s = 1 << sample_log2
+    total_items, total_s = 0, 0.0
+    for st, a in zip(streams, host):
+        for k in ks:
+            n = len(a)
+            c = max(1, round(chunks_of[(st.name, k)] * s / n))
+            t = time.perf_counter()
+            oracle.run(a[:s], k, c)
+            total_s += time.perf_counter() - t
+            total_items += s
+    return {
+        "value": total_items / total_s / 1e9,
+        "unit": "G items/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "first 2^%d items of each of the %d cases (same k, chunk count scaled to the sample), "
+                  "single-threaded C oracle; %.1f s of CPU work" % (sample_log2, len(streams) * len(ks), total_s),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="plain-large", choices=["plain-large", "plain"])
+    ap.add_argument("--n-log2", type=int, default=None)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-log2", type=int, default=24)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+    n_log2 = args.n_log2 if args.n_log2 is not None else (30 if args.workload == "plain-large" else 20)
+
+    import numpy as np
+    import torch
+    from paper_1606_04669_amd import binding as B
+
+    streams, ks = workload_cases(args.workload, n_log2, args.seed)
+    host, dev = [], []
+    for st in streams:
+        t = time.perf_counter()
+        a = st.generate()
+        log("generated %s n=2^%d in %.1fs" % (st.name, n_log2, time.perf_counter() - t))
+        host.append(a)
+        dev.append(torch.from_numpy(a.view(np.int32)).to("cuda"))
+    torch.cuda.synchronize()
+    ctx = B.Context(0)
+    chunks_of = {(st.name, k): ctx.plan_chunks(len(a), k) for st, a in zip(streams, host) for k in ks}
+    stream = torch.cuda.current_stream()
+
+    def step():
+        out = {}
+        for st, d in zip(streams, dev):
+            for k in ks:
+                got, used = B.pss_run(ctx, d, k=k, chunks=chunks_of[(st.name, k)], stream=stream)
+                out[(st.name, k)] = len(got)
+        return out
+
+    for i in range(args.warmup):
+        step()
+        log("warmup %d done" % i)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.phase_times(reset=True)
+    per_case_ms = {}
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        for st, d in zip(streams, dev):
+            for k in ks:
+                tc = time.perf_counter()
+                B.pss_run(ctx, d, k=k, chunks=chunks_of[(st.name, k)], stream=stream)
+                per_case_ms.setdefault((st.name, k), []).append((time.perf_counter() - tc) * 1e3)
+        log("step %d done" % i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms, launches = ctx.phase_times(reset=True)
+    ctx.timing(False)
+
+    items_per_step = sum(len(a) for a in host) * len(ks)
+    value = items_per_step * args.steps / elapsed / 1e9
+    n_items = len(host[0])
+    cs_avg_ms = ms[0] / max(1, launches[0])
+    achieved = 4.0 * n_items / (cs_avg_ms * 1e-3) / 1e9  # algorithmic bytes: 4 B per item
+    cases = []
+    for st in streams:
+        for k in ks:
+            t = sorted(per_case_ms[(st.name, k)])
+            med = t[len(t) // 2]
+            cases.append({"stream": st.name, "k": k, "chunks": chunks_of[(st.name, k)],
+                          "ms_median": round(med, 3), "g_items_per_s": round(n_items / med / 1e6, 2)})
+    total_ms = sum(ms)
+    result = {
+        "metric": "G items/s (plain single-stream Parallel Space Saving, 1 GPU)",
+        "value": round(value, 3),
+        "unit": "G items/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded Zipf/uniform uint32 streams, resident in HBM)",
+        "config": {
+            "workload": "%s: n=2^%d per stream, streams=%s, k=%s, chunks from the planner" % (
+                args.workload, n_log2, [s.name for s in streams], ks),
+            "n": n_items,
+            "cases": cases,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "chunk_summary_kernel",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "avg_launch_ms": round(cs_avg_ms, 4),
+            "launches": launches[0],
+        },
+        "phases_ms_per_step": {
+            "chunk_summary": round(ms[0] / args.steps, 3),
+            "combine_tree": round(ms[1] / args.steps, 3),
+            "fold": round(ms[2] / args.steps, 3),
+            "report": round(ms[3] / args.steps, 3),
+            "reduction_share": round((ms[1] + ms[2]) / total_ms, 4) if total_ms else None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        result["cpu_baseline"] = cpu_baseline(streams, ks, host, chunks_of, args.cpu_sample_log2)
+    print(json.dumps(result), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -133,6 +133,16 @@ int pss_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint3
                         const uint32_t* h_sel, uint32_t nsel, pss_entry* h_out, uint32_t* h_sizes,
                         uint64_t* h_mins, void* stream);
 
+/* Phase timing.  While enabled, pss_update, pss_run and pss_query record HIP
+ * events on the call's stream around each phase: 0 = block summaries
+ * (chunk_summary kernel), 1 = COMBINE tree, 2 = fold into the summary,
+ * 3 = report (extract kernel and copy to the host).  pss_phase_times waits
+ * for the recorded events, writes the accumulated milliseconds (ms[4]) and
+ * launch counts (launches[4]) since the last reset, and resets them when
+ * reset != 0.  Returns PSS_EINVAL for a null ctx. */
+int pss_timing_enable(pss_ctx* ctx, int enable);
+int pss_phase_times(pss_ctx* ctx, double* ms, uint32_t* launches, int reset);
+
 /* Static description of an error code. */
 const char* pss_strerror(int code);
 

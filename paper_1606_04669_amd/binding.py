@@ -58,7 +58,9 @@ def lib():
         L.pss_query.argtypes = [vp, i32, vp, u32, u32p, u64p, vp]
         L.pss_run.argtypes = [vp, vp, u64, u32, u32, vp, u32, u32p, u32p, vp]
         L.pss_block_summaries.argtypes = [vp, vp, u64, u32, u32, u32p, u32, vp, u32p, u64p, vp]
-        for f in ("pss_ctx_create", "pss_create", "pss_update", "pss_merge", "pss_query", "pss_run",
+        L.pss_timing_enable.argtypes = [vp, i32]
+        L.pss_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), u32p, i32]
+        for f in ("pss_timing_enable", "pss_phase_times", "pss_ctx_create", "pss_create", "pss_update", "pss_merge", "pss_query", "pss_run",
                   "pss_block_summaries"):
             getattr(L, f).restype = i32
         _lib = L
@@ -116,6 +118,16 @@ class Context:
 
     def plan_chunks(self, n: int, k: int) -> int:
         return int(lib().pss_plan_chunks(self.handle, n, k))
+
+    def timing(self, enable: bool):
+        _check(lib().pss_timing_enable(self.handle, 1 if enable else 0), "pss_timing_enable")
+
+    def phase_times(self, reset: bool = True):
+        """(ms[4], launches[4]) for block summaries, tree, fold, report."""
+        ms = (ctypes.c_double * 4)()
+        nl = (ctypes.c_uint32 * 4)()
+        _check(lib().pss_phase_times(self.handle, ms, nl, 1 if reset else 0), "pss_phase_times")
+        return list(ms), list(nl)
 
 
 def pss_ctx_create(device: int = 0) -> Context:

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <map>
+#include <vector>
 #include <mutex>
 #include <new>
 #include <string.h>
@@ -42,8 +43,18 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
 
+struct PhaseMark {
+    int phase;
+    hipEvent_t a, b;
+};
+
 struct pss_ctx {
     int device = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> event_pool;
+    std::vector<PhaseMark> marks;
+    double phase_ms[4] = {0, 0, 0, 0};
+    uint32_t phase_n[4] = {0, 0, 0, 0};
     int cu_count = 0;
     size_t lds_max = 0;      // dynamic LDS per workgroup
     size_t lds_per_cu = 0;
@@ -124,6 +135,43 @@ bool k_fits(const pss_ctx* ctx, uint32_t k) {
 
 int check(hipError_t e) { return e == hipSuccess ? PSS_OK : PSS_EDEVICE; }
 
+hipEvent_t take_event(pss_ctx* ctx) {
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records an event on the stream when timing is on; returns it (or null).
+hipEvent_t mark(pss_ctx* ctx, hipStream_t st) {
+    if (!ctx->timing) return nullptr;
+    hipEvent_t e = take_event(ctx);
+    if (e && hipEventRecord(e, st) != hipSuccess) {
+        ctx->event_pool.push_back(e);
+        return nullptr;
+    }
+    return e;
+}
+
+void close_phase(pss_ctx* ctx, int phase, hipEvent_t a, hipStream_t st) {
+    if (!a) return;
+    hipEvent_t b = mark(ctx, st);
+    if (!b) {
+        ctx->event_pool.push_back(a);
+        return;
+    }
+    try {
+        ctx->marks.push_back(PhaseMark{phase, a, b});
+    } catch (...) {
+        ctx->event_pool.push_back(a);
+        ctx->event_pool.push_back(b);
+    }
+}
+
 // block summaries of d_items[0, n) into the context workspace
 int run_blocks(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks, hipStream_t st,
                BlockSummaries* out) {
@@ -146,6 +194,39 @@ int ensure_pinned(pss_ctx* ctx, size_t bytes) {
 }  // namespace
 
 extern "C" {
+
+int pss_timing_enable(pss_ctx* ctx, int enable) {
+    if (!ctx) return PSS_EINVAL;
+    ctx->timing = enable != 0;
+    return PSS_OK;
+}
+
+int pss_phase_times(pss_ctx* ctx, double* ms, uint32_t* launches, int reset) {
+    if (!ctx) return PSS_EINVAL;
+    DeviceGuard g(ctx->device);
+    int rc = PSS_OK;
+    for (const PhaseMark& pm : ctx->marks) {
+        float t = 0.f;
+        if (hipEventSynchronize(pm.b) != hipSuccess || hipEventElapsedTime(&t, pm.a, pm.b) != hipSuccess)
+            rc = PSS_EDEVICE;
+        else {
+            ctx->phase_ms[pm.phase] += t;
+            ctx->phase_n[pm.phase] += 1;
+        }
+        ctx->event_pool.push_back(pm.a);
+        ctx->event_pool.push_back(pm.b);
+    }
+    ctx->marks.clear();
+    for (int i = 0; i < 4; ++i) {
+        if (ms) ms[i] = ctx->phase_ms[i];
+        if (launches) launches[i] = ctx->phase_n[i];
+        if (reset) {
+            ctx->phase_ms[i] = 0;
+            ctx->phase_n[i] = 0;
+        }
+    }
+    return rc;
+}
 
 const char* pss_strerror(int code) {
     switch (code) {
@@ -189,6 +270,8 @@ void pss_ctx_destroy(pss_ctx* ctx) {
     if (!ctx) return;
     DeviceGuard g(ctx->device);
     for (auto& kv : ctx->run_cache) pss_destroy(kv.second);
+    pss_phase_times(ctx, nullptr, nullptr, 1);
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     ctx->blocks.release();
     ctx->query.release();
     if (ctx->pinned) hipHostFree(ctx->pinned);
@@ -268,14 +351,23 @@ int pss_update(pss_summary* s, const uint32_t* d_items, uint64_t n, uint32_t chu
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
     BlockSummaries b;
-    int rc = run_blocks(ctx, d_items, n, k, C, st, &b);
+    int rc = ctx->blocks.grow(blocks_bytes(C, k));
     if (rc != PSS_OK) return rc;
+    b = carve_blocks(ctx->blocks.ptr, C, k);
+    hipEvent_t t0 = mark(ctx, st);
+    rc = check(launch_chunk_summary(d_items, n, C, k, b, st));
+    if (rc != PSS_OK) return rc;
+    close_phase(ctx, 0, t0, st);
+    hipEvent_t t1 = mark(ctx, st);
     for (uint32_t step = 1; step < C; step <<= 1) {
         rc = check(launch_combine_level(b, k, C, step, st));
         if (rc != PSS_OK) return rc;
     }
+    close_phase(ctx, 1, t1, st);
+    hipEvent_t t2 = mark(ctx, st);
     rc = check(launch_fold(s->view, b, k, st));
     if (rc != PSS_OK) return rc;
+    close_phase(ctx, 2, t2, st);
     s->n += n;
     if (chunks_used) *chunks_used = C;
     return PSS_OK;
@@ -308,10 +400,12 @@ int pss_query(const pss_summary* s, int kind, pss_entry* h_out, uint32_t cap, ui
     uint32_t* d_count = (uint32_t*)ctx->query.ptr;
     DevEntry* d_ent = (DevEntry*)((char*)ctx->query.ptr + 256);
     const uint32_t dev_cap = kind == PSS_Q_TOPK ? std::min(cap, k) : k;
+    hipEvent_t t3 = mark(ctx, st);
     rc = check(launch_extract(s->view, k, s->n, kind, dev_cap, d_ent, d_count, st));
     if (rc != PSS_OK) return rc;
     if (hipMemcpyAsync(ctx->pinned, ctx->query.ptr, qbytes, hipMemcpyDeviceToHost, st) != hipSuccess)
         return PSS_EDEVICE;
+    close_phase(ctx, 3, t3, st);
     if (hipStreamSynchronize(st) != hipSuccess) return PSS_EDEVICE;
     const uint32_t q = *(const uint32_t*)ctx->pinned;
     if (stream_len) *stream_len = s->n;

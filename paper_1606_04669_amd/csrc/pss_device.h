@@ -30,9 +30,32 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// DPP lane moves (GFX9 encodings): quad_perm, row mirrors and row broadcasts.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, Ctrl, RowMask, 0xF, false);
+}
+
+// Minimum over the 64 lanes, in uniform control flow with all lanes active.
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-    for (int off = 32; off > 0; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off));
-    return uniform(v);
+    v = min(v, dpp<0xB1, 0xF>(v));   // quad_perm [1,0,3,2]
+    v = min(v, dpp<0x4E, 0xF>(v));   // quad_perm [2,3,0,1]
+    v = min(v, dpp<0x141, 0xF>(v));  // row_half_mirror
+    v = min(v, dpp<0x140, 0xF>(v));  // row_mirror
+    v = min(v, dpp<0x142, 0xA>(v));  // row_bcast:15 into rows 1 and 3
+    v = min(v, dpp<0x143, 0xC>(v));  // row_bcast:31 into rows 2 and 3
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Sum over the 64 lanes, same pattern.
+__device__ __forceinline__ uint32_t wave_add_u32(uint32_t v) {
+    v += dpp<0xB1, 0xF>(v);
+    v += dpp<0x4E, 0xF>(v);
+    v += dpp<0x141, 0xF>(v);
+    v += dpp<0x140, 0xF>(v);
+    v += dpp<0x142, 0xA>(v);
+    v += dpp<0x143, 0xC>(v);
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {

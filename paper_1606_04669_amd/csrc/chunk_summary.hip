@@ -23,44 +23,162 @@
 //    next window at the first item it did not apply.  The first item of a
 //    window is always applicable, so every window makes progress.
 //
-// The counters at the minimum level are consumed through a list of at most
-// kListCap entries sorted by item id: the smallest ids of level m above the
-// last id already listed.  An entry stays usable while its counter still
-// holds that item at count m: counts never decrease and new items enter at
-// m+1, so no counter joins level m after the level is first listed.
+// The counters at the minimum level m are listed once, sorted by item id, when
+// the level is first needed.  A listed counter is still a victim candidate
+// exactly while its count is m: counts never decrease, an evicted counter is
+// re-installed at m+1, and no counter can join level m after it is listed.
+//
+// The hash is linear probing over 4-slot buckets (32 bytes, read with two
+// 16-byte LDS loads); deleted entries become tombstones that later inserts
+// reuse, and the table is rebuilt when live plus tombstone slots pass 3/4.
 #include "pss_device.h"
 #include "pss_layout.h"
 #include "pss_kernels.h"
 
 namespace pss {
 
+#ifdef PSS_KERNEL_STATS
+// analysis builds only: per-phase cycle and event counts summed over waves
+__device__ unsigned long long g_kstats[16];
+#define KSTAT_DECL unsigned long long ks_[16] = {0};
+#define KSTAT_ADD(i, v) (ks_[(i)] += (unsigned long long)(v))
+#define KSTAT_NOW() ((unsigned long long)clock64())
+#define KSTAT_FLUSH()                                                        \
+    if (lane == 0)                                                           \
+        for (int i_ = 0; i_ < 16; ++i_) atomicAdd(&g_kstats[i_], ks_[i_]);
+#else
+#define KSTAT_DECL
+#define KSTAT_ADD(i, v) ((void)0)
+#define KSTAT_NOW() 0ull
+#define KSTAT_FLUSH()
+#endif
+
 constexpr uint32_t kTagEmpty = 0u;
 constexpr uint32_t kTagTomb = 0xFFFFFFFFu;
 constexpr uint32_t kTagPend = 0x80000000u;
 constexpr uint64_t kTombEntry = (uint64_t)kTagTomb << 32;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+// Block summary size written when a loop bound that the algorithm guarantees
+// is exceeded (an internal invariant failed): the host reports a device error
+// instead of the kernel spinning.
+constexpr uint32_t kBlockFailed = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint64_t make_entry(uint32_t key, uint32_t tag) {
     return ((uint64_t)tag << 32) | key;
 }
 
-// Bitonic sort (ascending) of P (power of two) uint64 values by one wave.
-__device__ void wave_bitonic_sort_u64(uint64_t* a, uint32_t P, uint32_t lane) {
-    for (uint32_t size = 2; size <= P; size <<= 1) {
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t t = lane; t < P / 2; t += kWave) {
-                uint32_t i = 2 * t - (t & (stride - 1));
-                uint32_t j = i + stride;
-                bool up = (i & size) == 0;
-                uint64_t x = a[i], y = a[j];
-                if ((x > y) == up) {
-                    a[i] = y;
-                    a[j] = x;
+// Home bucket of an item: multiplicative hash scaled to nb buckets.
+__device__ __forceinline__ uint32_t home_bucket(uint32_t x, uint32_t nb) {
+    return (uint32_t)(((uint64_t)(x * 0x9E3779B1u) * nb) >> 32);
+}
+
+// ---------------------------------------------------------------------------
+// Sorting the minimum level by item id
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, uint32_t lx) {
+    uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, (int)lx);
+    uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), (int)lx);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of 64*P keys held in registers; element g lives in
+// lane g / P, register g % P.
+template <int P>
+__device__ __forceinline__ void reg_bitonic_sort(uint64_t (&v)[P], uint32_t lane) {
+    constexpr uint32_t N = 64u * P;
+    for (uint32_t size = 2; size <= N; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride >= (uint32_t)P; stride >>= 1) {
+            const uint32_t lx = stride / P;
+            const bool lower = (lane & lx) == 0;
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                const bool up = ((lane * P + j) & size) == 0;
+                const uint64_t o = shfl_xor_u64(v[j], lx);
+                const uint64_t mn = v[j] < o ? v[j] : o;
+                const uint64_t mx = v[j] < o ? o : v[j];
+                v[j] = (lower == up) ? mn : mx;
+            }
+        }
+#pragma unroll
+        for (int stride = P / 2; stride > 0; stride >>= 1) {
+            if ((uint32_t)stride < size) {
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    if ((j & stride) == 0) {
+                        const int j2 = j | stride;
+                        const bool up = ((lane * P + j) & size) == 0;
+                        const uint64_t a = v[j], b = v[j2];
+                        const bool sw = (a > b) == up;
+                        v[j] = sw ? b : a;
+                        v[j2] = sw ? a : b;
+                    }
                 }
             }
-            wave_sync();
         }
     }
 }
+
+// list[0, len) holds counter indices; reorder them by item id.
+template <int P>
+__device__ void sort_level_regs(uint16_t* list, const uint32_t* item, uint32_t len, uint32_t lane) {
+    uint64_t v[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const uint32_t g = lane * P + j;
+        v[j] = ~0ull;
+        if (g < len) {
+            const uint32_t s = list[g];
+            v[j] = ((uint64_t)item[s] << 32) | s;
+        }
+    }
+    reg_bitonic_sort<P>(v, lane);
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const uint32_t g = lane * P + j;
+        if (g < len) list[g] = (uint16_t)v[j];
+    }
+}
+
+template <int P>
+__device__ void sort_level_dispatch(uint16_t* list, const uint32_t* item, uint32_t len, uint32_t per_lane,
+                                    uint32_t lane) {
+    if constexpr (P >= 2) {
+        if (per_lane == (uint32_t)P) {
+            sort_level_regs<P>(list, item, len, lane);
+            return;
+        }
+        if constexpr (P > 2) sort_level_dispatch<P / 2>(list, item, len, per_lane, lane);
+    }
+}
+
+template <int P>
+__device__ void sort_level(uint16_t* list, const uint32_t* item, uint32_t len, uint32_t lane) {
+    if (len <= 64) {
+        // rank sort: one entry per lane, rank = number of smaller ids
+        uint32_t s = 0;
+        uint32_t key = 0xFFFFFFFFu;
+        if (lane < len) {
+            s = list[lane];
+            key = item[s];
+        }
+        uint32_t rank = 0;
+        for (uint32_t i = 0; i < len; ++i) {
+            const uint32_t ki = __builtin_amdgcn_readlane(key, i);
+            rank += ki < key ? 1u : 0u;
+        }
+        wave_sync();
+        if (lane < len) list[rank] = (uint16_t)s;
+    } else {
+        sort_level_dispatch<P>(list, item, len, next_pow2((len + 63) / 64), lane);
+    }
+    wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// Input staging
+// ---------------------------------------------------------------------------
 
 // Four consecutive items at idx (a multiple of 4), zero at and beyond stop.
 __device__ __forceinline__ uint4 load4(const uint32_t* __restrict__ items, uint64_t idx, uint64_t n, uint64_t stop,
@@ -96,41 +214,11 @@ __device__ __forceinline__ void store_half(uint32_t* ring, uint64_t tile, const 
     *(uint4*)(ring + base + 256 + 4 * lane) = p.b;
 }
 
-// Lane holding the bucket of a 256-bin histogram (4 bins per lane) that
-// contains the rank-th element; returns the bin and the rank inside it.
-__device__ __forceinline__ void hist_select(const uint32_t* hist, uint32_t rank, uint32_t lane, uint32_t* bin_out,
-                                            uint32_t* rank_out) {
-    uint32_t b0 = hist[4 * lane], b1 = hist[4 * lane + 1], b2 = hist[4 * lane + 2], b3 = hist[4 * lane + 3];
-    uint32_t s = b0 + b1 + b2 + b3, incl = s;
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t t = (uint32_t)__shfl_up((int)incl, off);
-        if ((int)lane >= off) incl += t;
-    }
-    uint32_t excl = incl - s;
-    bool here = excl <= rank && rank < incl;
-    uint32_t bin = 0, rr = 0;
-    if (here) {
-        rr = rank - excl;
-        bin = 4 * lane;
-        if (rr >= b0) {
-            rr -= b0;
-            ++bin;
-            if (rr >= b1) {
-                rr -= b1;
-                ++bin;
-                if (rr >= b2) {
-                    rr -= b2;
-                    ++bin;
-                }
-            }
-        }
-    }
-    const uint64_t hm = ballot(here);
-    const uint32_t src = (uint32_t)__builtin_ctzll(hm);
-    *bin_out = __builtin_amdgcn_readlane(bin, src);
-    *rank_out = __builtin_amdgcn_readlane(rr, src);
-}
+// ---------------------------------------------------------------------------
+// The kernel
+// ---------------------------------------------------------------------------
 
+template <int P>
 __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __restrict__ items, uint64_t n,
                                                            uint32_t chunks, ChunkLayout L, int vec_ok,
                                                            uint32_t* __restrict__ o_item,
@@ -142,32 +230,35 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
     const uint32_t lane = threadIdx.x;
     const uint32_t c = blockIdx.x;
     const uint32_t k = L.k;
+    const uint32_t T = L.tsize;
+    const uint32_t NB = L.nbuckets;
     uint64_t* table = (uint64_t*)(smem + L.off_table);
-    uint64_t* list = (uint64_t*)(smem + L.off_list);
-    uint32_t* hist = (uint32_t*)(smem + L.off_list);  // aliases the list while it is rebuilt
+    const uint4* tbl4 = (const uint4*)(smem + L.off_table);
     uint32_t* cnt = (uint32_t*)(smem + L.off_cnt);
     uint32_t* item = (uint32_t*)(smem + L.off_item);
     uint32_t* err = (uint32_t*)(smem + L.off_err);
     uint16_t* hpos = (uint16_t*)(smem + L.off_hpos);
+    uint16_t* list = (uint16_t*)(smem + L.off_list);
     uint8_t* mark = (uint8_t*)(smem + L.off_mark);
     uint32_t* ring = (uint32_t*)(smem + L.off_ring);
     uint32_t* vbuf = (uint32_t*)(smem + L.off_scratch);
-    uint8_t* posbuf = (uint8_t*)(vbuf + 64);
 
     // block bounds (Algorithm 1): [floor(c n / C), floor((c+1) n / C)), n < 2^32
     const uint64_t begin = (uint64_t)c * n / chunks;
     const uint64_t end = (uint64_t)(c + 1) * n / chunks;
-    const uint32_t tmask = L.tsize - 1;
     // rebuild the hash when live + tombstone slots pass 3/4 (always >= 65 empty)
-    const uint32_t tlimit = min(L.tsize - L.tsize / 4, L.tsize - 65);
+    const uint32_t tlimit = min(T - T / 4, T - 65);
 
-    for (uint32_t i = lane; i < L.tsize; i += kWave) table[i] = 0ull;
+    for (uint32_t i = lane; i < T; i += kWave) table[i] = 0ull;
     for (uint32_t i = lane; i < k; i += kWave) mark[i] = 0;
 
-    uint32_t size = 0, full = 0, tused = 0;
-    // minimum level: count m, listed entries [list_ptr, list_len), last id listed,
-    // and whether level m may hold counters with larger ids not yet listed
-    uint32_t m = 0, list_len = 0, list_ptr = 0, last_id = 0, more = 0;
+    // Wave-uniform state.  Every update goes through uniform() so the compiler
+    // keeps it in scalar registers and every loop that contains wave-wide
+    // operations (ballot, DPP, readlane, shuffles) has a uniform exit.
+    uint32_t size = 0, full = 0, tused = 0, failed = 0;
+    // minimum level: count m and its listed counters [list_ptr, list_len)
+    uint32_t m = 0, list_len = 0, list_ptr = 0;
+    uint32_t last_slow = 0;
 
     // input staging: the ring holds items [rbase, rbase + kRing)
     uint64_t rbase = begin & ~(uint64_t)(kRingHalf - 1);
@@ -180,67 +271,128 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
     Prefetch pf = fetch_half(items, rbase + kRing, n, end, vec_ok, lane);
     wave_sync();
 
+    KSTAT_DECL
+    const unsigned long long t_start = KSTAT_NOW();
     uint64_t pos = begin;
-    while (pos < end) {
+    while (pos < end && !failed) {
+        KSTAT_ADD(0, 1);
         if (pos >= rbase + kRingHalf) {
+            const unsigned long long t0 = KSTAT_NOW();
             store_half(ring, rbase + kRing, pf, lane);  // overwrites the consumed half
             rbase += kRingHalf;
             pf = fetch_half(items, rbase + kRing, n, end, vec_ok, lane);
             wave_sync();
+            KSTAT_ADD(9, KSTAT_NOW() - t0);
+            KSTAT_ADD(10, 1);
         }
+        const unsigned long long tw = KSTAT_NOW();
         if (tused > tlimit) {
             // drop tombstones: rebuild the hash from the live counters
+            KSTAT_ADD(8, 1);
             wave_sync();
-            for (uint32_t i = lane; i < L.tsize; i += kWave) table[i] = 0ull;
+            for (uint32_t i = lane; i < T; i += kWave) table[i] = 0ull;
             wave_sync();
+            bool bad = false;
             for (uint32_t s = lane; s < size; s += kWave) {
-                uint32_t x = item[s];
-                uint32_t h = hash_slot(x, L.tbits);
-                while (atomicCAS((unsigned long long*)&table[h], 0ull, (unsigned long long)make_entry(x, s + 1)) != 0ull)
-                    h = (h + 1) & tmask;
+                const uint32_t x = item[s];
+                uint32_t h = 4 * home_bucket(x, NB);
+                uint32_t steps = 0;
+                while (atomicCAS((unsigned long long*)&table[h], 0ull, (unsigned long long)make_entry(x, s + 1)) != 0ull) {
+                    h = (h + 1 == T) ? 0 : h + 1;
+                    if (++steps >= T) {
+                        bad = true;
+                        break;
+                    }
+                }
                 hpos[s] = (uint16_t)h;
             }
             wave_sync();
             tused = size;
+            if (ballot(bad)) {
+                failed = 1;
+                continue;
+            }
+            KSTAT_ADD(7, KSTAT_NOW() - tw);
         }
 
         const uint32_t wl = (uint32_t)((end - pos) < kWave ? (end - pos) : kWave);
         const bool valid = lane < wl;
         const uint32_t x = valid ? ring[(uint32_t)(pos + lane) & (kRing - 1)] : 0u;
 
-        // 1. look up against the state at window start; remember the first
-        //    tombstone on the probe path as the insertion point of a miss
+        // victims for this window (list entries list_ptr + lane), fetched early
+        // when the last window needed them.  The loads are unconditional on
+        // clamped indices: no divergent branch may separate the wave-wide
+        // operations of the victim loop below.
+        bool vinb = false;
+        uint32_t vs = 0, vcnt = 0, vhp = 0;
+        auto fetch_victims = [&]() {
+            const uint32_t li = list_ptr + lane;
+            vinb = li < list_len;
+            const uint32_t e = list[vinb ? li : 0u];
+            vs = vinb ? e : 0u;
+            vcnt = cnt[vs];
+            vhp = hpos[vs];
+        };
+        const bool early = last_slow && full && list_ptr < list_len;
+        if (early) fetch_victims();
+
+        // 1. look up against the state at window start, 4 slots per step; a
+        //    miss inserts at the first free (tombstone or empty) slot it passed
         bool hit = false, miss = false;
         uint32_t slot = 0, hp = 0;
+        bool bad = false;
         if (valid) {
-            uint32_t h = hash_slot(x, L.tbits);
-            uint32_t first_free = 0xFFFFFFFFu;
+            uint32_t b = home_bucket(x, NB);
+            uint32_t first_free = kNone;
+            uint32_t steps = 0;
             for (;;) {
-                const uint64_t e = table[h];
-                const uint32_t tag = (uint32_t)(e >> 32);
-                if (tag == kTagEmpty) {
-                    miss = true;
+                const uint4 q0 = tbl4[2 * b];
+                const uint4 q1 = tbl4[2 * b + 1];
+                const uint32_t keys[4] = {q0.x, q0.z, q1.x, q1.z};
+                const uint32_t tags[4] = {q0.y, q0.w, q1.y, q1.w};
+                bool done = false;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (!done) {
+                        if (tags[i] == kTagEmpty) {
+                            if (first_free == kNone) first_free = 4 * b + i;
+                            miss = true;
+                            done = true;
+                        } else if (tags[i] == kTagTomb) {
+                            if (first_free == kNone) first_free = 4 * b + i;
+                        } else if (keys[i] == x) {
+                            hit = true;
+                            slot = tags[i] - 1u;
+                            done = true;
+                        }
+                    }
+                }
+                if (done) break;
+                b = (b + 1 == NB) ? 0 : b + 1;
+                if (++steps >= NB) {  // the table always keeps empty slots
+                    bad = true;
                     break;
                 }
-                if (tag == kTagTomb) {
-                    if (first_free == 0xFFFFFFFFu) first_free = h;
-                } else if ((uint32_t)e == x) {
-                    hit = true;
-                    slot = tag - 1u;
-                    break;
-                }
-                h = (h + 1) & tmask;
             }
-            hp = (miss && first_free != 0xFFFFFFFFu) ? first_free : h;
+            hp = first_free;
+        }
+        if (ballot(bad)) {
+            failed = 1;
+            continue;
         }
 
         const uint64_t missmask = ballot(miss);
+        KSTAT_ADD(15, KSTAT_NOW() - tw);
         if (missmask == 0) {
             // all hits: increments commute
             if (hit) atomicAdd(&cnt[slot], 1u);
             pos += wl;
+            last_slow = 0;
+            KSTAT_ADD(1, 1);
+            KSTAT_ADD(2, KSTAT_NOW() - tw);
             continue;
         }
+        last_slow = 1;
 
         // 2. group unmonitored items by value: one pending hash entry per value,
         //    tagged with the lowest lane holding it
@@ -248,6 +400,7 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
         if (miss) {
             const uint64_t mine = make_entry(x, kTagPend | lane);
             uint32_t h = hp;
+            uint32_t steps = 0;
             for (;;) {
                 uint64_t e = table[h];
                 uint32_t tag = (uint32_t)(e >> 32);
@@ -265,119 +418,94 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
                     atomicMin(((uint32_t*)&table[h]) + 1, kTagPend | lane);
                     break;
                 }
-                h = (h + 1) & tmask;
+                h = (h + 1 == T) ? 0 : h + 1;
+                if (++steps >= T) {
+                    bad = true;
+                    break;
+                }
             }
             hp = h;
         }
-        wave_sync();
-        const uint32_t rep = miss ? (((const volatile uint32_t*)&table[hp])[1] & 63u) : lane;
-        const uint64_t newmask = ballot(miss && rep == lane);
-        const bool newf = (newmask >> lane) & 1ull;
-        const uint32_t r = popc64(newmask);
-        const uint32_t nrank = mbcnt(newmask);
-        tused += popc64(ballot(took_empty));
-        if (newf) posbuf[nrank] = (uint8_t)lane;
+        if (ballot(bad)) {
+            failed = 1;
+            continue;
+        }
 
-        // 3. counters the new items will take: free ones, or victims at level m
-        uint32_t avail = 0;
+        // 3. victims: the counters of level m in id order, from the list
+        uint32_t avail = 0, vr = 0;
         uint64_t vmask = 0;
-        uint32_t vs = 0, vr = 0;
         bool vv = false;
         if (!full) {
             avail = k - size;
         } else {
+            if (!early) fetch_victims();
+            // at most one pass over the listed entries plus one rebuild
+            uint32_t guard = list_len / kWave + 3;
             for (;;) {
-                if (list_ptr >= list_len) {
-                    // list the next counters of the minimum level, by id
-                    uint32_t lo = 0;
-                    bool fresh = !more || last_id == 0xFFFFFFFFu;
-                    if (!fresh) lo = last_id + 1;
-                    uint32_t cand = 0;
-                    for (int attempt = 0; attempt < 2; ++attempt) {
-                        if (fresh) {
-                            uint32_t mn = 0xFFFFFFFFu;
-                            for (uint32_t s = lane; s < k; s += kWave) mn = min(mn, cnt[s]);
-                            m = wave_min_u32(mn);
-                            lo = 0;
-                        }
-                        uint32_t cl = 0;
-                        for (uint32_t s = lane; s < k; s += kWave) cl += (cnt[s] == m && item[s] >= lo) ? 1u : 0u;
-                        cand = wave_add_u32(cl);
-                        if (cand > 0) break;
-                        fresh = true;  // level m holds nothing above lo: move to the new minimum
-                    }
-                    // ids above lo at level m: take the kListCap smallest
-                    uint32_t hi = 0xFFFFFFFFu;
-                    if (cand > kListCap) {
-                        uint32_t prefix = 0, rank = kListCap - 1;
-                        for (int d = 3; d >= 0; --d) {
-                            const uint32_t sh = 8u * (uint32_t)d;
-                            const uint32_t pm = (d == 3) ? 0u : (0xFFFFFFFFu << (sh + 8));
-                            for (uint32_t i = lane; i < 256; i += kWave) hist[i] = 0u;
-                            wave_sync();
-                            for (uint32_t s = lane; s < k; s += kWave) {
-                                const uint32_t it = item[s];
-                                if (cnt[s] == m && it >= lo && (it & pm) == prefix)
-                                    atomicAdd(&hist[(it >> sh) & 255u], 1u);
-                            }
-                            wave_sync();
-                            uint32_t bin, rr;
-                            hist_select(hist, rank, lane, &bin, &rr);
-                            prefix |= bin << sh;
-                            rank = rr;
-                            wave_sync();
-                        }
-                        hi = prefix;
-                    }
+                vv = vinb && vcnt == m;
+                vmask = ballot(vv);
+                if (vmask) break;
+                if (guard-- == 0) {
+                    failed = 1;
+                    break;
+                }
+                if (list_ptr + kWave < list_len) {
+                    list_ptr = uniform(list_ptr + kWave);
+                } else {
+                    // level exhausted: list the new minimum level, by id
+                    const unsigned long long tl = KSTAT_NOW();
+                    KSTAT_ADD(5, 1);
+                    uint32_t mn = 0xFFFFFFFFu;
+                    for (uint32_t s = lane; s < k; s += kWave) mn = min(mn, cnt[s]);
+                    m = uniform(wave_min_u32(mn));
                     uint32_t len = 0;
                     for (uint32_t b = 0; b < k; b += kWave) {
                         const uint32_t s = b + lane;
-                        bool take = false;
-                        uint32_t it = 0;
-                        if (s < k) {
-                            it = item[s];
-                            take = cnt[s] == m && it >= lo && it <= hi;
-                        }
+                        const bool take = s < k && cnt[s] == m;
                         const uint64_t bm = ballot(take);
-                        if (take) list[len + mbcnt(bm)] = ((uint64_t)it << 32) | s;
-                        len += popc64(bm);
+                        if (take) list[len + mbcnt(bm)] = (uint16_t)s;
+                        len = uniform(len + popc64(bm));
                     }
-                    uint32_t P = next_pow2(len);
-                    if (P < 2) P = 2;
-                    for (uint32_t i = len + lane; i < P; i += kWave) list[i] = ~0ull;
                     wave_sync();
-                    wave_bitonic_sort_u64(list, P, lane);
+                    sort_level<P>(list, item, len, lane);
                     list_len = len;
                     list_ptr = 0;
-                    last_id = (uint32_t)(list[len - 1] >> 32);
-                    more = cand > len;
+                    KSTAT_ADD(4, KSTAT_NOW() - tl);
                 }
-                const uint32_t li = list_ptr + lane;
-                const bool inb = li < list_len;
-                const uint64_t le = inb ? list[li] : 0ull;
-                vs = (uint32_t)le;
-                vv = inb && item[vs] == (uint32_t)(le >> 32) && cnt[vs] == m;
-                vmask = ballot(vv);
-                if (vmask) break;
-                list_ptr = (list_ptr + kWave < list_len) ? list_ptr + kWave : list_len;
+                fetch_victims();
             }
+            if (failed) continue;
             avail = popc64(vmask);
             vr = mbcnt(vmask);
-            if (vv && vr < r) {
-                vbuf[vr] = vs;
+            if (vv) {
+                vbuf[vr] = vs | (vhp << 16);
                 mark[vs] = (uint8_t)(vr + 1);
             }
         }
         wave_sync();
 
+        const uint32_t rep = miss ? (((const volatile uint32_t*)&table[hp])[1] & 63u) : lane;
+        const uint32_t jmark = (hit && full) ? mark[slot] : 0u;
+        const uint64_t newmask = ballot(miss && rep == lane);
+        const bool newf = (newmask >> lane) & 1ull;
+        const uint32_t r = popc64(newmask);
+        const uint32_t nrank = mbcnt(newmask);
+        tused = uniform(tused + popc64(ballot(took_empty)));
+
         // 4. longest prefix with no conflict
         uint32_t cpos = wl;
         if (newf && nrank >= avail) cpos = lane;
-        if (hit && full) {
-            const uint32_t j = mark[slot];
-            if (j) cpos = max(lane, (uint32_t)posbuf[j - 1]);
+        if (jmark != 0 && jmark - 1 < r) {
+            // the hit and the eviction of the same counter cannot both be applied
+            uint64_t mm = newmask;
+            for (uint32_t t = 0; t + 1 < jmark; ++t) mm &= mm - 1;
+            cpos = max(lane, (uint32_t)__builtin_ctzll(mm));
         }
-        const uint32_t p = ballot(cpos < wl) ? wave_min_u32(cpos) : wl;
+        const uint32_t p = uniform(ballot(cpos < wl) ? wave_min_u32(cpos) : wl);
+        if (p == 0) {  // the first item of a window is always applicable
+            failed = 1;
+            continue;
+        }
         const bool in = lane < p;
 
         // 5. apply the prefix
@@ -390,8 +518,9 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
                     cnt[myslot] = 1u;
                     err[myslot] = 0u;
                 } else {
-                    myslot = vbuf[nrank];
-                    table[hpos[myslot]] = kTombEntry;
+                    const uint32_t vb = vbuf[nrank];
+                    myslot = vb & 0xFFFFu;
+                    table[vb >> 16] = kTombEntry;
                     cnt[myslot] = m + 1u;
                     err[myslot] = m;
                 }
@@ -408,28 +537,39 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
             const uint32_t rslot = (uint32_t)__shfl((int)myslot, (int)rep);
             if (repeat) atomicAdd(&cnt[rslot], 1u);
         }
-        if (vv && vr < r) mark[vs] = 0;
+        if (vv) mark[vs] = 0;
 
         const uint64_t inmask = (p >= kWave) ? ~0ull : ((1ull << p) - 1ull);
         const uint32_t rp = popc64(newmask & inmask);
         if (!full) {
-            size += rp;
+            size = uniform(size + rp);
             if (size == k) {
                 full = 1;
                 list_len = 0;
                 list_ptr = 0;
-                more = 0;
             }
         } else if (rp > 0) {
             const uint64_t lastm = ballot(vv && vr == rp - 1);
-            list_ptr += (uint32_t)__builtin_ctzll(lastm) + 1u;
+            list_ptr = uniform(list_ptr + (uint32_t)__builtin_ctzll(lastm) + 1u);
         }
         pos += p;
         wave_sync();
+        KSTAT_ADD(3, KSTAT_NOW() - tw);
+        KSTAT_ADD(11, p < wl ? 1 : 0);
+        KSTAT_ADD(14, r);
     }
+    KSTAT_ADD(12, KSTAT_NOW() - t_start);
+    KSTAT_FLUSH();
 
     // write the summary and its minimum (0 while fewer than k counters are used)
     wave_sync();
+    if (failed) {
+        if (lane == 0) {
+            o_size[c] = kBlockFailed;
+            o_min[c] = 0;
+        }
+        return;
+    }
     uint32_t mo = 0;
     if (full) {
         uint32_t mn = 0xFFFFFFFFu;
@@ -448,19 +588,48 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
     }
 }
 
-hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t chunks, uint32_t k,
-                                const BlockSummaries& out, hipStream_t stream) {
-    ChunkLayout L = ChunkLayout::make(k);
-    int vec_ok = ((uintptr_t)d_items & 15u) == 0;
-    hipFuncSetAttribute((const void*)chunk_summary_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.bytes);
-    hipLaunchKernelGGL(chunk_summary_kernel, dim3(chunks), dim3(64), L.bytes, stream, d_items, n, chunks, L, vec_ok,
-                       out.item, out.cnt, out.err, out.size, out.min);
+#ifdef PSS_KERNEL_STATS
+extern "C" int pss_debug_kstats(unsigned long long* out, int reset) {
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_kstats), sizeof(g_kstats)) != hipSuccess) return -6;
+    if (reset) {
+        unsigned long long z[16] = {0};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_kstats), z, sizeof(z)) != hipSuccess) return -6;
+    }
+    return 0;
+}
+#endif
+
+template <int P>
+static hipError_t launch_p(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L, int vec_ok,
+                           const BlockSummaries& out, hipStream_t stream) {
+    hipFuncSetAttribute((const void*)chunk_summary_kernel<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)L.bytes);
+    hipLaunchKernelGGL(chunk_summary_kernel<P>, dim3(chunks), dim3(64), L.bytes, stream, d_items, n, chunks, L,
+                       vec_ok, out.item, out.cnt, out.err, out.size, out.min);
     return hipGetLastError();
 }
 
+hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t chunks, uint32_t k,
+                                const BlockSummaries& out, hipStream_t stream) {
+    const ChunkLayout L = ChunkLayout::make(k);
+    if (!L.valid()) return hipErrorInvalidValue;
+    const int vec_ok = ((uintptr_t)d_items & 15u) == 0;
+    switch (sort_lanes_per_k(k)) {
+    case 1:
+    case 2: return launch_p<2>(d_items, n, chunks, L, vec_ok, out, stream);
+    case 4: return launch_p<4>(d_items, n, chunks, L, vec_ok, out, stream);
+    case 8: return launch_p<8>(d_items, n, chunks, L, vec_ok, out, stream);
+    case 16: return launch_p<16>(d_items, n, chunks, L, vec_ok, out, stream);
+    case 32: return launch_p<32>(d_items, n, chunks, L, vec_ok, out, stream);
+    case 64: return launch_p<64>(d_items, n, chunks, L, vec_ok, out, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 uint32_t chunk_summary_lds_bytes(uint32_t k) {
-    ChunkLayout L = ChunkLayout::make(k);
-    return L.tsize <= 65536 ? L.bytes : 0xFFFFFFFFu;
+    const ChunkLayout L = ChunkLayout::make(k);
+    if (!L.valid() || sort_lanes_per_k(k) > 64) return 0xFFFFFFFFu;
+    return L.bytes;
 }
 
 }  // namespace pss

@@ -75,6 +75,14 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
     const uint32_t hbits = log2_pow2(L.hsize);
     const uint32_t hmask = L.hsize - 1;
     const CO m1 = (CO)m1_, m2 = (CO)m2_;
+    if (n1 > k || n2 > k) {
+        // an input summary carries the failure mark of a block kernel: pass it on
+        if (tid == 0) {
+            *osize = 0xFFFFFFFFu;
+            *omin = 0;
+        }
+        return;
+    }
     const uint32_t nc = n1 + n2;
 
     // stage S2 as candidates [n1, n1 + n2): items only in S2 get + m1

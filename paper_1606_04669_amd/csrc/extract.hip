@@ -33,6 +33,10 @@ __global__ __launch_bounds__(kExtractThreads) void extract_kernel(WideSummary s,
     uint32_t* ci = (uint32_t*)(ce + P0);
     const uint32_t tid = threadIdx.x;
     const uint32_t size = s.size[0];
+    if (size > k) {  // the summary carries the failure mark of a block kernel
+        if (tid == 0) *out_count = 0xFFFFFFFFu;
+        return;
+    }
     uint32_t P = next_pow2(size);
     if (P < 2) P = 2;
     for (uint32_t i = tid; i < P; i += kExtractThreads) {

@@ -408,6 +408,7 @@ int pss_query(const pss_summary* s, int kind, pss_entry* h_out, uint32_t cap, ui
     close_phase(ctx, 3, t3, st);
     if (hipStreamSynchronize(st) != hipSuccess) return PSS_EDEVICE;
     const uint32_t q = *(const uint32_t*)ctx->pinned;
+    if (q > k) return PSS_EDEVICE;  // a kernel reported a failed invariant
     if (stream_len) *stream_len = s->n;
     *n_out = q;
     if (kind == PSS_Q_MAJORITY && q > cap) return PSS_ETRUNC;

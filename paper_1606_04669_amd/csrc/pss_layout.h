@@ -15,8 +15,8 @@ namespace pss {
 // Items staged per half of the LDS input ring (two halves).
 constexpr uint32_t kRingHalf = 512;
 constexpr uint32_t kRing = 2 * kRingHalf;
-// Capacity of the sorted list of minimum-level counters (victims in order).
-constexpr uint32_t kListCap = 512;
+// Largest hash table (slot positions are stored as uint16).
+constexpr uint32_t kMaxTableSlots = 65536;
 
 PSS_HD inline uint32_t next_pow2(uint32_t v) {
     uint32_t p = 1;
@@ -30,35 +30,43 @@ PSS_HD inline uint32_t log2_pow2(uint32_t p) {
     return b;
 }
 
+// Registers per lane the victim-list sort needs for k counters.
+PSS_HD inline uint32_t sort_lanes_per_k(uint32_t k) {
+    return next_pow2((k + 63) / 64);
+}
+
 struct ChunkLayout {
     uint32_t k;
-    uint32_t tbits;   // hash table has 2^tbits slots
-    uint32_t tsize;
+    uint32_t nbuckets;  // hash buckets of 4 slots
+    uint32_t tsize;     // 4 * nbuckets slots
     // byte offsets inside the wave's LDS block
-    uint32_t off_table, off_list, off_cnt, off_item, off_err, off_hpos, off_mark, off_ring, off_scratch;
+    uint32_t off_table, off_cnt, off_item, off_err, off_hpos, off_list, off_mark, off_ring, off_scratch;
     uint32_t bytes;
 
-    // hash_shift: table size = next_pow2(2k) << hash_shift (load factor knob;
-    // it changes speed and LDS use, never results)
-    PSS_HD static ChunkLayout make(uint32_t k, uint32_t hash_shift = 0) {
+    // slots_per_counter (x16): hash slots per counter; a speed / LDS knob
+    // that never changes results.
+    PSS_HD static ChunkLayout make(uint32_t k, uint32_t slots_per_counter_x16 = 32) {
         ChunkLayout L;
         L.k = k;
-        L.tsize = next_pow2(2 * k) << hash_shift;
-        if (L.tsize < 256) L.tsize = 256;
-        L.tbits = log2_pow2(L.tsize);
+        uint32_t slots = (k * slots_per_counter_x16 + 15) / 16;
+        if (slots < 256) slots = 256;
+        L.nbuckets = (slots + 3) / 4;
+        L.tsize = 4 * L.nbuckets;
         uint32_t o = 0;
-        L.off_table = o;   o += 8 * L.tsize;           // uint64 entries (key | tag << 32)
-        L.off_list = o;    o += 8 * kListCap;          // uint64 (item << 32 | slot); histogram while rebuilding
+        L.off_table = o;   o += 8 * L.tsize;           // uint64 entries (key | tag << 32), 32 B buckets
         L.off_cnt = o;     o += 4 * ((k + 3) & ~3u);
         L.off_item = o;    o += 4 * ((k + 3) & ~3u);
         L.off_err = o;     o += 4 * ((k + 3) & ~3u);
-        L.off_hpos = o;    o += 2 * ((k + 7) & ~7u);   // uint16 table position of each counter
+        L.off_hpos = o;    o += 2 * ((k + 7) & ~7u);   // uint16 table slot of each counter
+        L.off_list = o;    o += 2 * ((k + 7) & ~7u);   // uint16 counters of the minimum level, by id
         L.off_mark = o;    o += (k + 15) & ~15u;       // uint8 victim ranks
         L.off_ring = o;    o += 4 * kRing;             // staged input items
-        L.off_scratch = o; o += 4 * 64 + 64;           // victim slots [64] (u32), positions [64] (u8)
+        L.off_scratch = o; o += 4 * 64;                // victim slot | table slot << 16, per rank
         L.bytes = o;
         return L;
     }
+
+    PSS_HD bool valid() const { return tsize <= kMaxTableSlots; }
 };
 
 }  // namespace pss

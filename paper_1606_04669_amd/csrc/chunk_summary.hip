@@ -336,45 +336,37 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
         const bool early = last_slow && full && list_ptr < list_len;
         if (early) fetch_victims();
 
-        // 1. look up against the state at window start, 4 slots per step; a
-        //    miss inserts at the first free (tombstone or empty) slot it passed
-        bool hit = false, miss = false;
-        uint32_t slot = 0, hp = 0;
-        bool bad = false;
-        if (valid) {
+        // 1. look up against the state at window start, one 4-slot bucket per
+        //    step (branch-free inside a step); a miss inserts at the first free
+        //    (tombstone or empty) slot it passed
+        bool hit = false, miss = false, bad = false;
+        uint32_t slot = 0, hp = kNone;
+        {
             uint32_t b = home_bucket(x, NB);
-            uint32_t first_free = kNone;
             uint32_t steps = 0;
-            for (;;) {
+            bool go = valid;
+            while (go) {
                 const uint4 q0 = tbl4[2 * b];
                 const uint4 q1 = tbl4[2 * b + 1];
-                const uint32_t keys[4] = {q0.x, q0.z, q1.x, q1.z};
-                const uint32_t tags[4] = {q0.y, q0.w, q1.y, q1.w};
-                bool done = false;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    if (!done) {
-                        if (tags[i] == kTagEmpty) {
-                            if (first_free == kNone) first_free = 4 * b + i;
-                            miss = true;
-                            done = true;
-                        } else if (tags[i] == kTagTomb) {
-                            if (first_free == kNone) first_free = 4 * b + i;
-                        } else if (keys[i] == x) {
-                            hit = true;
-                            slot = tags[i] - 1u;
-                            done = true;
-                        }
-                    }
-                }
-                if (done) break;
+                // live tags are counter index + 1 in [1, 2^31): (tag - 1) < 2^31 - 1
+                const uint32_t em = (q0.y == kTagEmpty ? 1u : 0u) | (q0.w == kTagEmpty ? 2u : 0u) |
+                                    (q1.y == kTagEmpty ? 4u : 0u) | (q1.w == kTagEmpty ? 8u : 0u);
+                const uint32_t fm = em | (q0.y == kTagTomb ? 1u : 0u) | (q0.w == kTagTomb ? 2u : 0u) |
+                                    (q1.y == kTagTomb ? 4u : 0u) | (q1.w == kTagTomb ? 8u : 0u);
+                const uint32_t hm = ((q0.x == x && q0.y - 1u < 0x7FFFFFFFu) ? 1u : 0u) |
+                                    ((q0.z == x && q0.w - 1u < 0x7FFFFFFFu) ? 2u : 0u) |
+                                    ((q1.x == x && q1.y - 1u < 0x7FFFFFFFu) ? 4u : 0u) |
+                                    ((q1.z == x && q1.w - 1u < 0x7FFFFFFFu) ? 8u : 0u);
+                if (hp == kNone && fm != 0u) hp = 4 * b + (uint32_t)__builtin_ctz(fm);
+                const uint32_t tag = (hm & 1u) ? q0.y : (hm & 2u) ? q0.w : (hm & 4u) ? q1.y : q1.w;
+                hit = hm != 0u;
+                slot = tag - 1u;
+                miss = !hit && em != 0u;
                 b = (b + 1 == NB) ? 0 : b + 1;
-                if (++steps >= NB) {  // the table always keeps empty slots
-                    bad = true;
-                    break;
-                }
+                ++steps;
+                bad = steps >= NB && !hit && !miss;  // the table always keeps empty slots
+                go = !hit && !miss && !bad;
             }
-            hp = first_free;
         }
         if (ballot(bad)) {
             failed = 1;

@@ -153,8 +153,100 @@ __device__ void sort_level_dispatch(uint16_t* list, const uint32_t* item, uint32
     }
 }
 
+// Largest bucket the bucketed sort ranks directly; beyond it the level is
+// sorted with the register network instead.
+constexpr uint32_t kMaxBucket = 48;
+
+// Bucketed sort of list[0, len) by item id for len > 64, 64 * P >= len:
+// a counting sort on 8 bits of the id (the top 8 of the bits where the
+// level's ids differ, so bucket order is id order), then every entry's rank
+// inside its bucket.  Returns false, leaving list untouched, when a bucket is
+// larger than kMaxBucket.
 template <int P>
-__device__ void sort_level(uint16_t* list, const uint32_t* item, uint32_t len, uint32_t lane) {
+__device__ bool sort_level_buckets(uint16_t* list, const uint32_t* item, uint32_t* tkey, uint32_t* hist,
+                                   uint32_t len, uint32_t lane) {
+    uint32_t sd[P], id[P], pin[P];
+    uint32_t orv = 0u, andv = 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const uint32_t g = lane * P + j;
+        const uint32_t s = list[g < len ? g : 0u];
+        id[j] = item[s];
+        sd[j] = s;
+        if (g < len) {
+            orv |= id[j];
+            andv &= id[j];
+        }
+    }
+    const uint32_t diff = wave_or_u32(orv) ^ wave_and_u32(andv);
+    const uint32_t hb = 31u - (uint32_t)__builtin_clz(diff | 1u);
+    const uint32_t shift = hb >= 7u ? hb - 7u : 0u;
+    for (uint32_t i = lane; i < 257; i += kWave) hist[i] = 0u;
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const uint32_t g = lane * P + j;
+        const uint32_t d = (id[j] >> shift) & 255u;
+        sd[j] |= d << 16;
+        pin[j] = (g < len) ? atomicAdd(&hist[d], 1u) : 0u;
+    }
+    wave_sync();
+    const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+    if (wave_max_u32(max(max(h0, h1), max(h2, h3))) > kMaxBucket) return false;
+    // exclusive scan of the 256 counts: bucket d occupies [hist[d], hist[d+1])
+    const uint32_t sum = h0 + h1 + h2 + h3;
+    uint32_t incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
+        if ((int)lane >= off) incl += t;
+    }
+    const uint32_t ex = incl - sum;
+    wave_sync();
+    hist[4 * lane] = ex;
+    hist[4 * lane + 1] = ex + h0;
+    hist[4 * lane + 2] = ex + h0 + h1;
+    hist[4 * lane + 3] = ex + h0 + h1 + h2;
+    if (lane == 63) hist[256] = incl;
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const uint32_t g = lane * P + j;
+        if (g < len) tkey[hist[sd[j] >> 16] + pin[j]] = id[j];
+    }
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const uint32_t g = lane * P + j;
+        if (g < len) {
+            const uint32_t d = sd[j] >> 16;
+            const uint32_t b0 = hist[d], b1 = hist[d + 1];
+            uint32_t r = 0;
+            for (uint32_t t = b0; t < b1; ++t) r += tkey[t] < id[j] ? 1u : 0u;
+            pin[j] = b0 + r;
+        }
+    }
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const uint32_t g = lane * P + j;
+        if (g < len) list[pin[j]] = (uint16_t)(sd[j] & 0xFFFFu);
+    }
+    return true;
+}
+
+template <int P>
+__device__ bool sort_level_buckets_dispatch(uint16_t* list, const uint32_t* item, uint32_t* tkey, uint32_t* hist,
+                                            uint32_t len, uint32_t per_lane, uint32_t lane) {
+    if constexpr (P >= 2 && P <= 32) {
+        if (per_lane == (uint32_t)P) return sort_level_buckets<P>(list, item, tkey, hist, len, lane);
+    }
+    if constexpr (P > 2) return sort_level_buckets_dispatch<P / 2>(list, item, tkey, hist, len, per_lane, lane);
+    return false;
+}
+
+template <int P>
+__device__ void sort_level(uint16_t* list, const uint32_t* item, uint32_t* tkey, uint32_t* hist, uint32_t len,
+                           uint32_t lane) {
     if (len <= 64) {
         // rank sort: one entry per lane, rank = number of smaller ids
         uint32_t s = 0;
@@ -171,7 +263,11 @@ __device__ void sort_level(uint16_t* list, const uint32_t* item, uint32_t len, u
         wave_sync();
         if (lane < len) list[rank] = (uint16_t)s;
     } else {
-        sort_level_dispatch<P>(list, item, len, next_pow2((len + 63) / 64), lane);
+        const uint32_t per_lane = next_pow2((len + 63) / 64);
+        if (!sort_level_buckets_dispatch<P>(list, item, tkey, hist, len, per_lane, lane)) {
+            wave_sync();
+            sort_level_dispatch<P>(list, item, len, per_lane, lane);
+        }
     }
     wave_sync();
 }
@@ -242,6 +338,8 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
     uint8_t* mark = (uint8_t*)(smem + L.off_mark);
     uint32_t* ring = (uint32_t*)(smem + L.off_ring);
     uint32_t* vbuf = (uint32_t*)(smem + L.off_scratch);
+    uint32_t* tkey = (uint32_t*)(smem + L.off_tkey);
+    uint32_t* hist = (uint32_t*)(smem + L.off_hist);
 
     // block bounds (Algorithm 1): [floor(c n / C), floor((c+1) n / C)), n < 2^32
     const uint64_t begin = (uint64_t)c * n / chunks;
@@ -459,7 +557,7 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
                         len = uniform(len + popc64(bm));
                     }
                     wave_sync();
-                    sort_level<P>(list, item, len, lane);
+                    sort_level<P>(list, item, tkey, hist, len, lane);
                     list_len = len;
                     list_ptr = 0;
                     KSTAT_ADD(4, KSTAT_NOW() - tl);

@@ -47,6 +47,37 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
     return __builtin_amdgcn_readlane(v, 63);
 }
 
+// Maximum, bitwise or and bitwise and over the 64 lanes, same pattern.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    v = max(v, dpp<0xB1, 0xF>(v));
+    v = max(v, dpp<0x4E, 0xF>(v));
+    v = max(v, dpp<0x141, 0xF>(v));
+    v = max(v, dpp<0x140, 0xF>(v));
+    v = max(v, dpp<0x142, 0xA>(v));
+    v = max(v, dpp<0x143, 0xC>(v));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t v) {
+    v |= dpp<0xB1, 0xF>(v);
+    v |= dpp<0x4E, 0xF>(v);
+    v |= dpp<0x141, 0xF>(v);
+    v |= dpp<0x140, 0xF>(v);
+    v |= dpp<0x142, 0xA>(v);
+    v |= dpp<0x143, 0xC>(v);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ uint32_t wave_and_u32(uint32_t v) {
+    v &= dpp<0xB1, 0xF>(v);
+    v &= dpp<0x4E, 0xF>(v);
+    v &= dpp<0x141, 0xF>(v);
+    v &= dpp<0x140, 0xF>(v);
+    v &= dpp<0x142, 0xA>(v);
+    v &= dpp<0x143, 0xC>(v);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 // Sum over the 64 lanes, same pattern.
 __device__ __forceinline__ uint32_t wave_add_u32(uint32_t v) {
     v += dpp<0xB1, 0xF>(v);

@@ -40,14 +40,20 @@ struct ChunkLayout {
     uint32_t nbuckets;  // hash buckets of 4 slots
     uint32_t tsize;     // 4 * nbuckets slots
     // byte offsets inside the wave's LDS block
-    uint32_t off_table, off_cnt, off_item, off_err, off_hpos, off_list, off_mark, off_ring, off_scratch;
+    uint32_t off_table, off_cnt, off_item, off_err, off_hpos, off_list, off_mark, off_ring, off_scratch, off_tkey,
+        off_hist;
     uint32_t bytes;
 
+    // Default hash slots per counter (x16): more room (shorter probes, fewer
+    // rebuilds) while the LDS footprint is small, 2 per counter for large k.
+    PSS_HD static uint32_t default_slots_x16(uint32_t k) { return k <= 1024 ? 64 : 32; }
+
     // slots_per_counter (x16): hash slots per counter; a speed / LDS knob
-    // that never changes results.
-    PSS_HD static ChunkLayout make(uint32_t k, uint32_t slots_per_counter_x16 = 32) {
+    // that never changes results (0 = default_slots_x16).
+    PSS_HD static ChunkLayout make(uint32_t k, uint32_t slots_per_counter_x16 = 0) {
         ChunkLayout L;
         L.k = k;
+        if (slots_per_counter_x16 == 0) slots_per_counter_x16 = default_slots_x16(k);
         uint32_t slots = (k * slots_per_counter_x16 + 15) / 16;
         if (slots < 256) slots = 256;
         L.nbuckets = (slots + 3) / 4;
@@ -62,6 +68,9 @@ struct ChunkLayout {
         L.off_mark = o;    o += (k + 15) & ~15u;       // uint8 victim ranks
         L.off_ring = o;    o += 4 * kRing;             // staged input items
         L.off_scratch = o; o += 4 * 64;                // victim slot | table slot << 16, per rank
+        L.off_tkey = o;    o += 4 * ((k + 3) & ~3u);   // ids in bucket order while a level is sorted
+        L.off_hist = o;    o += 4 * 257;               // bucket counts / starts while a level is sorted
+        o = (o + 15) & ~15u;
         L.bytes = o;
         return L;
     }

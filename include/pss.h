@@ -36,6 +36,9 @@
  * Errors: every int-returning function returns PSS_OK (0) or a negative
  * PSS_E* code and never throws.  A failed call leaves summaries unchanged.
  * Handles are not thread-safe: serialise calls on one summary or context.
+ * A context's workspace (block summaries, scratch) is shared by the calls
+ * made with it: queue them on one stream, or synchronise between calls made
+ * on different streams.
  */
 #ifndef PSS_H
 #define PSS_H
@@ -72,8 +75,14 @@ enum {
     PSS_Q_TOPK = 1      /* the first `cap` entries in canonical order */
 };
 
-/* Largest k the in-LDS kernels accept for this context (device dependent). */
+/* Largest k this library accepts (2^20; 0 for a null ctx).  Above
+ * pss_max_lds_k() a block's state (hash, counters, minimum-level list) lives
+ * in a device-memory slab instead of LDS; results are the same either way. */
 uint32_t pss_max_k(const pss_ctx* ctx);
+
+/* Largest k whose block state fits one workgroup's LDS on this context's
+ * device (0 for a null ctx). */
+uint32_t pss_max_lds_k(const pss_ctx* ctx);
 
 /* Create a context on HIP device `device`.  *out receives the handle.
  * Returns PSS_EINVAL (bad device / null out), PSS_EDEVICE or PSS_ENOMEM. */

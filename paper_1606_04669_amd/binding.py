@@ -48,6 +48,8 @@ def lib():
         L.pss_ctx_destroy.restype = None
         L.pss_max_k.restype = u32
         L.pss_max_k.argtypes = [vp]
+        L.pss_max_lds_k.restype = u32
+        L.pss_max_lds_k.argtypes = [vp]
         L.pss_plan_chunks.restype = u32
         L.pss_plan_chunks.argtypes = [vp, u64, u32]
         L.pss_create.argtypes = [vp, u32, ctypes.POINTER(vp)]
@@ -115,6 +117,10 @@ class Context:
     @property
     def max_k(self) -> int:
         return int(lib().pss_max_k(self.handle))
+
+    @property
+    def max_lds_k(self) -> int:
+        return int(lib().pss_max_lds_k(self.handle))
 
     def plan_chunks(self, n: int, k: int) -> int:
         return int(lib().pss_plan_chunks(self.handle, n, k))

@@ -31,6 +31,8 @@
 // The hash is linear probing over 4-slot buckets (32 bytes, read with two
 // 16-byte LDS loads); deleted entries become tombstones that later inserts
 // reuse, and the table is rebuilt when live plus tombstone slots pass 3/4.
+#include <type_traits>
+
 #include "pss_device.h"
 #include "pss_layout.h"
 #include "pss_kernels.h"
@@ -244,24 +246,94 @@ __device__ bool sort_level_buckets_dispatch(uint16_t* list, const uint32_t* item
     return false;
 }
 
+// Rank sort of list[0, len) by item id, len <= 64: one entry per lane, its
+// rank is the number of smaller ids.
+template <typename IT>
+__device__ void sort_level_rank(IT* list, const uint32_t* item, uint32_t len, uint32_t lane) {
+    uint32_t s = 0;
+    uint32_t key = 0xFFFFFFFFu;
+    if (lane < len) {
+        s = list[lane];
+        key = item[s];
+    }
+    uint32_t rank = 0;
+    for (uint32_t i = 0; i < len; ++i) {
+        const uint32_t ki = __builtin_amdgcn_readlane(key, i);
+        rank += ki < key ? 1u : 0u;
+    }
+    wave_sync();
+    if (lane < len) list[rank] = (IT)s;
+}
+
+// Stable least-significant-digit radix sort of list[0, len) by item id (four
+// 8-bit passes), for levels of any size.  Within each group of 64 entries the
+// lanes holding the same digit are found with eight ballots, so equal digits
+// keep their order.  list2, tkey and tkey2 hold len entries each.
+template <typename IT>
+__device__ void sort_level_radix(IT* list, IT* list2, const uint32_t* item, uint32_t* tkey, uint32_t* tkey2,
+                                 uint32_t* hist, uint32_t len, uint32_t lane) {
+    for (uint32_t g = lane; g < len; g += kWave) tkey[g] = item[list[g]];
+    wave_sync();
+    IT* src = list;
+    IT* dst = list2;
+    uint32_t* ks = tkey;
+    uint32_t* kd = tkey2;
+    for (uint32_t pass = 0; pass < 4; ++pass) {
+        const uint32_t sh = 8u * pass;
+        for (uint32_t i = lane; i < 256; i += kWave) hist[i] = 0u;
+        wave_sync();
+        for (uint32_t g = lane; g < len; g += kWave) atomicAdd(&hist[(ks[g] >> sh) & 255u], 1u);
+        wave_sync();
+        const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+        const uint32_t sum = h0 + h1 + h2 + h3;
+        uint32_t incl = sum;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
+            if ((int)lane >= off) incl += t;
+        }
+        const uint32_t ex = incl - sum;
+        wave_sync();
+        hist[4 * lane] = ex;
+        hist[4 * lane + 1] = ex + h0;
+        hist[4 * lane + 2] = ex + h0 + h1;
+        hist[4 * lane + 3] = ex + h0 + h1 + h2;
+        wave_sync();
+        for (uint32_t base = 0; base < len; base += kWave) {
+            const uint32_t g = base + lane;
+            const bool v = g < len;
+            const uint32_t key = ks[v ? g : 0u];
+            const IT sv = src[v ? g : 0u];
+            const uint32_t d = (key >> sh) & 255u;
+            uint64_t same = ballot(v);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const uint64_t bb = ballot(v && ((d >> b) & 1u));
+                same &= ((d >> b) & 1u) ? bb : ~bb;
+            }
+            const uint32_t rank = mbcnt(same);
+            const uint32_t off = hist[d];
+            wave_sync();
+            if (v && rank == 0) hist[d] = off + popc64(same);
+            if (v) {
+                dst[off + rank] = sv;
+                kd[off + rank] = key;
+            }
+            wave_sync();
+        }
+        IT* t1 = src;
+        src = dst;
+        dst = t1;
+        uint32_t* t2 = ks;
+        ks = kd;
+        kd = t2;
+    }
+}
+
 template <int P>
 __device__ void sort_level(uint16_t* list, const uint32_t* item, uint32_t* tkey, uint32_t* hist, uint32_t len,
                            uint32_t lane) {
     if (len <= 64) {
-        // rank sort: one entry per lane, rank = number of smaller ids
-        uint32_t s = 0;
-        uint32_t key = 0xFFFFFFFFu;
-        if (lane < len) {
-            s = list[lane];
-            key = item[s];
-        }
-        uint32_t rank = 0;
-        for (uint32_t i = 0; i < len; ++i) {
-            const uint32_t ki = __builtin_amdgcn_readlane(key, i);
-            rank += ki < key ? 1u : 0u;
-        }
-        wave_sync();
-        if (lane < len) list[rank] = (uint16_t)s;
+        sort_level_rank<uint16_t>(list, item, len, lane);
     } else {
         const uint32_t per_lane = next_pow2((len + 63) / 64);
         if (!sort_level_buckets_dispatch<P>(list, item, tkey, hist, len, per_lane, lane)) {
@@ -314,31 +386,45 @@ __device__ __forceinline__ void store_half(uint32_t* ring, uint64_t tile, const 
 // The kernel
 // ---------------------------------------------------------------------------
 
-template <int P>
+// P: registers per lane for the in-register level sort (LDS-resident state);
+// G: the per-block state lives in global memory (slab gstate + c * state_bytes)
+// with 32-bit indices, for k whose state does not fit LDS.
+template <int P, bool G>
 __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __restrict__ items, uint64_t n,
                                                            uint32_t chunks, ChunkLayout L, int vec_ok,
                                                            uint32_t* __restrict__ o_item,
                                                            uint32_t* __restrict__ o_cnt,
                                                            uint32_t* __restrict__ o_err,
                                                            uint32_t* __restrict__ o_size,
-                                                           uint32_t* __restrict__ o_min) {
+                                                           uint32_t* __restrict__ o_min,
+                                                           unsigned char* __restrict__ gstate) {
+    using idx_t = typename std::conditional<G, uint32_t, uint16_t>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t lane = threadIdx.x;
     const uint32_t c = blockIdx.x;
     const uint32_t k = L.k;
     const uint32_t T = L.tsize;
     const uint32_t NB = L.nbuckets;
-    uint64_t* table = (uint64_t*)(smem + L.off_table);
-    const uint4* tbl4 = (const uint4*)(smem + L.off_table);
-    uint32_t* cnt = (uint32_t*)(smem + L.off_cnt);
-    uint32_t* item = (uint32_t*)(smem + L.off_item);
-    uint32_t* err = (uint32_t*)(smem + L.off_err);
-    uint16_t* hpos = (uint16_t*)(smem + L.off_hpos);
-    uint16_t* list = (uint16_t*)(smem + L.off_list);
-    uint8_t* mark = (uint8_t*)(smem + L.off_mark);
+    unsigned char* sb;
+    if constexpr (G) {
+        sb = gstate + (size_t)c * L.state_bytes;
+    } else {
+        sb = smem;
+    }
+    uint64_t* table = (uint64_t*)(sb + L.off_table);
+    const uint4* tbl4 = (const uint4*)(sb + L.off_table);
+    uint32_t* cnt = (uint32_t*)(sb + L.off_cnt);
+    uint32_t* item = (uint32_t*)(sb + L.off_item);
+    uint32_t* err = (uint32_t*)(sb + L.off_err);
+    idx_t* hpos = (idx_t*)(sb + L.off_hpos);
+    idx_t* list = (idx_t*)(sb + L.off_list);
+    uint8_t* mark = (uint8_t*)(sb + L.off_mark);
+    uint32_t* tkey = (uint32_t*)(sb + L.off_tkey);
+    idx_t* list2 = (idx_t*)(sb + L.off_list2);
+    uint32_t* tkey2 = (uint32_t*)(sb + L.off_tkey2);
     uint32_t* ring = (uint32_t*)(smem + L.off_ring);
-    uint32_t* vbuf = (uint32_t*)(smem + L.off_scratch);
-    uint32_t* tkey = (uint32_t*)(smem + L.off_tkey);
+    uint32_t* vslot = (uint32_t*)(smem + L.off_vslot);
+    uint32_t* vhpos = (uint32_t*)(smem + L.off_vhpos);
     uint32_t* hist = (uint32_t*)(smem + L.off_hist);
 
     // block bounds (Algorithm 1): [floor(c n / C), floor((c+1) n / C)), n < 2^32
@@ -402,7 +488,7 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
                         break;
                     }
                 }
-                hpos[s] = (uint16_t)h;
+                hpos[s] = (idx_t)h;
             }
             wave_sync();
             tused = size;
@@ -553,11 +639,19 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
                         const uint32_t s = b + lane;
                         const bool take = s < k && cnt[s] == m;
                         const uint64_t bm = ballot(take);
-                        if (take) list[len + mbcnt(bm)] = (uint16_t)s;
+                        if (take) list[len + mbcnt(bm)] = (idx_t)s;
                         len = uniform(len + popc64(bm));
                     }
                     wave_sync();
-                    sort_level<P>(list, item, tkey, hist, len, lane);
+                    if constexpr (G) {
+                        if (len <= 64)
+                            sort_level_rank<idx_t>(list, item, len, lane);
+                        else
+                            sort_level_radix<idx_t>(list, list2, item, tkey, tkey2, hist, len, lane);
+                        wave_sync();
+                    } else {
+                        sort_level<P>(list, item, tkey, hist, len, lane);
+                    }
                     list_len = len;
                     list_ptr = 0;
                     KSTAT_ADD(4, KSTAT_NOW() - tl);
@@ -568,7 +662,8 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
             avail = popc64(vmask);
             vr = mbcnt(vmask);
             if (vv) {
-                vbuf[vr] = vs | (vhp << 16);
+                vslot[vr] = vs;
+                vhpos[vr] = vhp;
                 mark[vs] = (uint8_t)(vr + 1);
             }
         }
@@ -608,14 +703,13 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
                     cnt[myslot] = 1u;
                     err[myslot] = 0u;
                 } else {
-                    const uint32_t vb = vbuf[nrank];
-                    myslot = vb & 0xFFFFu;
-                    table[vb >> 16] = kTombEntry;
+                    myslot = vslot[nrank];
+                    table[vhpos[nrank]] = kTombEntry;
                     cnt[myslot] = m + 1u;
                     err[myslot] = m;
                 }
                 item[myslot] = x;
-                hpos[myslot] = (uint16_t)hp;
+                hpos[myslot] = (idx_t)hp;
                 table[hp] = make_entry(x, myslot + 1u);
             } else {
                 table[hp] = kTombEntry;  // not applied: retire the pending entry
@@ -689,37 +783,39 @@ extern "C" int pss_debug_kstats(unsigned long long* out, int reset) {
 }
 #endif
 
-template <int P>
+template <int P, bool G>
 static hipError_t launch_p(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L, int vec_ok,
-                           const BlockSummaries& out, hipStream_t stream) {
-    hipFuncSetAttribute((const void*)chunk_summary_kernel<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)L.bytes);
-    hipLaunchKernelGGL(chunk_summary_kernel<P>, dim3(chunks), dim3(64), L.bytes, stream, d_items, n, chunks, L,
-                       vec_ok, out.item, out.cnt, out.err, out.size, out.min);
+                           const BlockSummaries& out, unsigned char* gstate, hipStream_t stream) {
+    hipFuncSetAttribute((const void*)chunk_summary_kernel<P, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)L.lds_bytes);
+    hipLaunchKernelGGL((chunk_summary_kernel<P, G>), dim3(chunks), dim3(64), L.lds_bytes, stream, d_items, n, chunks,
+                       L, vec_ok, out.item, out.cnt, out.err, out.size, out.min, gstate);
     return hipGetLastError();
 }
 
-hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t chunks, uint32_t k,
-                                const BlockSummaries& out, hipStream_t stream) {
-    const ChunkLayout L = ChunkLayout::make(k);
-    if (!L.valid()) return hipErrorInvalidValue;
-    const int vec_ok = ((uintptr_t)d_items & 15u) == 0;
-    switch (sort_lanes_per_k(k)) {
-    case 1:
-    case 2: return launch_p<2>(d_items, n, chunks, L, vec_ok, out, stream);
-    case 4: return launch_p<4>(d_items, n, chunks, L, vec_ok, out, stream);
-    case 8: return launch_p<8>(d_items, n, chunks, L, vec_ok, out, stream);
-    case 16: return launch_p<16>(d_items, n, chunks, L, vec_ok, out, stream);
-    case 32: return launch_p<32>(d_items, n, chunks, L, vec_ok, out, stream);
-    case 64: return launch_p<64>(d_items, n, chunks, L, vec_ok, out, stream);
-    default: return hipErrorInvalidValue;
-    }
+ChunkLayout chunk_layout(uint32_t k, size_t lds_max) {
+    const ChunkLayout L = ChunkLayout::make(k, false);
+    if (L.fits_lds_indices() && L.lds_bytes <= lds_max && sort_lanes_per_k(k) <= 64) return L;
+    return ChunkLayout::make(k, true);
 }
 
-uint32_t chunk_summary_lds_bytes(uint32_t k) {
-    const ChunkLayout L = ChunkLayout::make(k);
-    if (!L.valid() || sort_lanes_per_k(k) > 64) return 0xFFFFFFFFu;
-    return L.bytes;
+hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L,
+                                const BlockSummaries& out, unsigned char* gstate, hipStream_t stream) {
+    const int vec_ok = ((uintptr_t)d_items & 15u) == 0;
+    if (L.global_state) {
+        if (!gstate) return hipErrorInvalidValue;
+        return launch_p<1, true>(d_items, n, chunks, L, vec_ok, out, gstate, stream);
+    }
+    switch (sort_lanes_per_k(L.k)) {
+    case 1:
+    case 2: return launch_p<2, false>(d_items, n, chunks, L, vec_ok, out, nullptr, stream);
+    case 4: return launch_p<4, false>(d_items, n, chunks, L, vec_ok, out, nullptr, stream);
+    case 8: return launch_p<8, false>(d_items, n, chunks, L, vec_ok, out, nullptr, stream);
+    case 16: return launch_p<16, false>(d_items, n, chunks, L, vec_ok, out, nullptr, stream);
+    case 32: return launch_p<32, false>(d_items, n, chunks, L, vec_ok, out, nullptr, stream);
+    case 64: return launch_p<64, false>(d_items, n, chunks, L, vec_ok, out, nullptr, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace pss

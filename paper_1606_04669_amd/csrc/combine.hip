@@ -19,11 +19,15 @@ namespace pss {
 constexpr uint32_t kCombineThreads = 256;
 constexpr uint8_t kAlive = 1, kCand = 2;
 
+// Storage of one COMBINE: the candidate arrays and the S2 hash ("big",
+// O(k)) live in LDS when they fit, else in a global slab per node; the
+// radix-select histogram ("small") is always in LDS.
 template <typename CO>
 struct CombineLds {
     uint32_t cap;   // candidate capacity (2k)
     uint32_t hsize; // S2 hash slots
-    uint32_t off_cc, off_ce, off_ci, off_flag, off_hash, off_hist, off_misc, bytes;
+    uint32_t off_cc, off_ce, off_ci, off_flag, off_hash, big_bytes;
+    uint32_t off_hist, off_misc, off_red, small_bytes;
 
     __host__ __device__ static CombineLds make(uint32_t k) {
         CombineLds L;
@@ -31,14 +35,16 @@ struct CombineLds {
         L.hsize = next_pow2(2 * k);
         if (L.hsize < 64) L.hsize = 64;
         uint32_t o = 0;
-        L.off_cc = o;   o += sizeof(CO) * L.cap;
-        L.off_ce = o;   o += sizeof(CO) * L.cap;
-        L.off_ci = o;   o += 4 * L.cap;
-        L.off_flag = o; o += (L.cap + 15) & ~15u;
-        L.off_hash = o; o += 4 * L.hsize;
-        L.off_hist = o; o += 4 * 256;
-        L.off_misc = o; o += 64;
-        L.bytes = o;
+        L.off_cc = o;   o = align16(o + sizeof(CO) * L.cap);
+        L.off_ce = o;   o = align16(o + sizeof(CO) * L.cap);
+        L.off_ci = o;   o = align16(o + 4 * L.cap);
+        L.off_flag = o; o = align16(o + L.cap);
+        L.off_hash = o; o = align16(o + 4 * L.hsize);
+        L.big_bytes = o;
+        L.off_hist = 0;
+        L.off_misc = 4 * 256;
+        L.off_red = L.off_misc + 64;
+        L.small_bytes = L.off_red + 8 * (kCombineThreads / kWave);
         return L;
     }
 };
@@ -62,15 +68,16 @@ __device__ __forceinline__ bool better(CO ca, CO ea, uint32_t ia, CO cb, CO eb, 
 template <typename C1, typename C2, typename CO>
 __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uint32_t n1, C1 m1_,
                              const uint32_t* i2, const C2* c2, const C2* e2, uint32_t n2, C2 m2_, uint32_t k,
-                             uint32_t* io, CO* co, CO* eo, uint32_t* osize, CO* omin, unsigned char* smem) {
+                             uint32_t* io, CO* co, CO* eo, uint32_t* osize, CO* omin, unsigned char* big,
+                             unsigned char* small) {
     const CombineLds<CO> L = CombineLds<CO>::make(k);
-    CO* cc = (CO*)(smem + L.off_cc);
-    CO* ce = (CO*)(smem + L.off_ce);
-    uint32_t* ci = (uint32_t*)(smem + L.off_ci);
-    uint8_t* flag = (uint8_t*)(smem + L.off_flag);
-    uint32_t* hash = (uint32_t*)(smem + L.off_hash);
-    uint32_t* hist = (uint32_t*)(smem + L.off_hist);
-    uint32_t* misc = (uint32_t*)(smem + L.off_misc);
+    CO* cc = (CO*)(big + L.off_cc);
+    CO* ce = (CO*)(big + L.off_ce);
+    uint32_t* ci = (uint32_t*)(big + L.off_ci);
+    uint8_t* flag = (uint8_t*)(big + L.off_flag);
+    uint32_t* hash = (uint32_t*)(big + L.off_hash);
+    uint32_t* hist = (uint32_t*)(small + L.off_hist);
+    uint32_t* misc = (uint32_t*)(small + L.off_misc);
     const uint32_t tid = threadIdx.x;
     const uint32_t hbits = log2_pow2(L.hsize);
     const uint32_t hmask = L.hsize - 1;
@@ -220,7 +227,7 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
     const uint32_t kept = misc[0];
     // minimum of the result: 0 unless all k counters are used
     CO wmin = wave_min_u64((uint64_t)local_min);
-    __shared__ uint64_t red[kCombineThreads / kWave];
+    uint64_t* red = (uint64_t*)(small + L.off_red);
     if (lane_id() == 0) red[tid / kWave] = (uint64_t)wmin;
     __syncthreads();
     if (tid == 0) {
@@ -231,55 +238,103 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
     }
 }
 
+// One workgroup per pair of the level, or (global storage) a bounded grid
+// whose workgroups each reuse one scratch slab for pairs blockIdx, blockIdx +
+// gridDim, ...
+template <bool G>
 __global__ __launch_bounds__(kCombineThreads) void combine_level_kernel(BlockSummaries v, uint32_t k, uint32_t count,
-                                                                        uint32_t step) {
+                                                                        uint32_t step, uint32_t pairs,
+                                                                        unsigned char* scratch, uint32_t big_bytes) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const uint64_t a = 2ull * step * blockIdx.x;
-    const uint64_t b = a + step;
-    if (b >= count) return;
-    combine_node<uint32_t, uint32_t, uint32_t>(v.item + a * k, v.cnt + a * k, v.err + a * k, v.size[a], v.min[a],
-                                               v.item + b * k, v.cnt + b * k, v.err + b * k, v.size[b], v.min[b], k,
-                                               v.item + a * k, v.cnt + a * k, v.err + a * k, &v.size[a], &v.min[a],
-                                               smem);
+    unsigned char* big = G ? scratch + (uint64_t)blockIdx.x * big_bytes : smem + CombineLds<uint32_t>::make(k).small_bytes;
+    for (uint32_t j = blockIdx.x; j < pairs; j += gridDim.x) {
+        const uint64_t a = 2ull * step * j;
+        const uint64_t b = a + step;
+        __syncthreads();  // the previous pair is done with the slab
+        combine_node<uint32_t, uint32_t, uint32_t>(v.item + a * k, v.cnt + a * k, v.err + a * k, v.size[a], v.min[a],
+                                                   v.item + b * k, v.cnt + b * k, v.err + b * k, v.size[b], v.min[b],
+                                                   k, v.item + a * k, v.cnt + a * k, v.err + a * k, &v.size[a],
+                                                   &v.min[a], big, smem);
+    }
 }
 
-__global__ __launch_bounds__(kCombineThreads) void fold_kernel(WideSummary d, BlockSummaries s, uint32_t k) {
+template <bool G>
+__global__ __launch_bounds__(kCombineThreads) void fold_kernel(WideSummary d, BlockSummaries s, uint32_t k,
+                                                               unsigned char* scratch) {
     extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char* big = G ? scratch : smem + CombineLds<uint64_t>::make(k).small_bytes;
     combine_node<uint64_t, uint32_t, uint64_t>(d.item, d.cnt, d.err, d.size[0], d.min[0], s.item, s.cnt, s.err,
-                                               s.size[0], s.min[0], k, d.item, d.cnt, d.err, d.size, d.min, smem);
+                                               s.size[0], s.min[0], k, d.item, d.cnt, d.err, d.size, d.min, big, smem);
 }
 
-__global__ __launch_bounds__(kCombineThreads) void merge_kernel(WideSummary d, WideSummary s, uint32_t k) {
+template <bool G>
+__global__ __launch_bounds__(kCombineThreads) void merge_kernel(WideSummary d, WideSummary s, uint32_t k,
+                                                                unsigned char* scratch) {
     extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char* big = G ? scratch : smem + CombineLds<uint64_t>::make(k).small_bytes;
     combine_node<uint64_t, uint64_t, uint64_t>(d.item, d.cnt, d.err, d.size[0], d.min[0], s.item, s.cnt, s.err,
-                                               s.size[0], s.min[0], k, d.item, d.cnt, d.err, d.size, d.min, smem);
+                                               s.size[0], s.min[0], k, d.item, d.cnt, d.err, d.size, d.min, big, smem);
 }
 
 uint32_t combine_lds_bytes(uint32_t k, bool wide) {
-    return wide ? CombineLds<uint64_t>::make(k).bytes : CombineLds<uint32_t>::make(k).bytes;
+    return wide ? CombineLds<uint64_t>::make(k).big_bytes + CombineLds<uint64_t>::make(k).small_bytes
+                : CombineLds<uint32_t>::make(k).big_bytes + CombineLds<uint32_t>::make(k).small_bytes;
 }
 
-hipError_t launch_combine_level(const BlockSummaries& v, uint32_t k, uint32_t count, uint32_t step,
-                                hipStream_t stream) {
+size_t combine_scratch_bytes(uint32_t k, bool wide) {
+    return wide ? CombineLds<uint64_t>::make(k).big_bytes : CombineLds<uint32_t>::make(k).big_bytes;
+}
+
+hipError_t launch_combine_level(const BlockSummaries& v, uint32_t k, uint32_t count, uint32_t step, bool in_lds,
+                                unsigned char* scratch, uint32_t slabs, hipStream_t stream) {
     if (step >= count) return hipSuccess;
-    const uint32_t pairs = (count - step + 2 * step - 1) / (2 * step);
-    const uint32_t lds = CombineLds<uint32_t>::make(k).bytes;
-    hipFuncSetAttribute((const void*)combine_level_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(combine_level_kernel, dim3(pairs), dim3(kCombineThreads), lds, stream, v, k, count, step);
+    // pairs (a, a + step) with a = 2 step j and a + step < count
+    const uint32_t pairs = (uint32_t)(((uint64_t)count - step + 2ull * step - 1) / (2ull * step));
+    const CombineLds<uint32_t> L = CombineLds<uint32_t>::make(k);
+    if (in_lds) {
+        const uint32_t lds = L.big_bytes + L.small_bytes;
+        hipFuncSetAttribute((const void*)combine_level_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+        hipLaunchKernelGGL(combine_level_kernel<false>, dim3(pairs), dim3(kCombineThreads), lds, stream, v, k, count,
+                           step, pairs, (unsigned char*)nullptr, 0u);
+    } else {
+        if (!scratch || slabs == 0) return hipErrorInvalidValue;
+        const uint32_t grid = pairs < slabs ? pairs : slabs;
+        hipLaunchKernelGGL(combine_level_kernel<true>, dim3(grid), dim3(kCombineThreads), L.small_bytes, stream, v, k,
+                           count, step, pairs, scratch, L.big_bytes);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_fold(const WideSummary& dst, const BlockSummaries& src, uint32_t k, hipStream_t stream) {
-    const uint32_t lds = CombineLds<uint64_t>::make(k).bytes;
-    hipFuncSetAttribute((const void*)fold_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(kCombineThreads), lds, stream, dst, src, k);
+hipError_t launch_fold(const WideSummary& dst, const BlockSummaries& src, uint32_t k, bool in_lds,
+                       unsigned char* scratch, hipStream_t stream) {
+    const CombineLds<uint64_t> L = CombineLds<uint64_t>::make(k);
+    if (in_lds) {
+        const uint32_t lds = L.big_bytes + L.small_bytes;
+        hipFuncSetAttribute((const void*)fold_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(fold_kernel<false>, dim3(1), dim3(kCombineThreads), lds, stream, dst, src, k,
+                           (unsigned char*)nullptr);
+    } else {
+        if (!scratch) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(fold_kernel<true>, dim3(1), dim3(kCombineThreads), L.small_bytes, stream, dst, src, k,
+                           scratch);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_merge(const WideSummary& dst, const WideSummary& src, uint32_t k, hipStream_t stream) {
-    const uint32_t lds = CombineLds<uint64_t>::make(k).bytes;
-    hipFuncSetAttribute((const void*)merge_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(merge_kernel, dim3(1), dim3(kCombineThreads), lds, stream, dst, src, k);
+hipError_t launch_merge(const WideSummary& dst, const WideSummary& src, uint32_t k, bool in_lds,
+                        unsigned char* scratch, hipStream_t stream) {
+    const CombineLds<uint64_t> L = CombineLds<uint64_t>::make(k);
+    if (in_lds) {
+        const uint32_t lds = L.big_bytes + L.small_bytes;
+        hipFuncSetAttribute((const void*)merge_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(merge_kernel<false>, dim3(1), dim3(kCombineThreads), lds, stream, dst, src, k,
+                           (unsigned char*)nullptr);
+    } else {
+        if (!scratch) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(merge_kernel<true>, dim3(1), dim3(kCombineThreads), L.small_bytes, stream, dst, src, k,
+                           scratch);
+    }
     return hipGetLastError();
 }
 

@@ -15,7 +15,13 @@ __host__ __device__ inline uint32_t extract_cap(uint32_t k) {
     return P < 2 ? 2 : P;
 }
 
-uint32_t extract_lds_bytes(uint32_t k) { return extract_cap(k) * (8 + 8 + 4); }
+// Sort arrays (count, error, item) of next_pow2(k) entries, then 16 bytes of
+// small shared state, which stays in LDS when the arrays go to scratch.
+__host__ __device__ inline uint32_t extract_big_bytes(uint32_t k) { return extract_cap(k) * (8 + 8 + 4); }
+constexpr uint32_t kExtractSmallBytes = 16;
+
+uint32_t extract_lds_bytes(uint32_t k) { return extract_big_bytes(k) + kExtractSmallBytes; }
+size_t extract_scratch_bytes(uint32_t k) { return extract_big_bytes(k); }
 
 __device__ __forceinline__ bool ext_better(uint64_t ca, uint64_t ea, uint32_t ia, uint64_t cb, uint64_t eb,
                                            uint32_t ib) {
@@ -24,11 +30,16 @@ __device__ __forceinline__ bool ext_better(uint64_t ca, uint64_t ea, uint32_t ia
     return ia < ib;
 }
 
+// G: the sort arrays live in a global scratch slab (k beyond LDS).
+template <bool G>
 __global__ __launch_bounds__(kExtractThreads) void extract_kernel(WideSummary s, uint32_t k, uint64_t N, int kind,
-                                                                  uint32_t cap, DevEntry* out, uint32_t* out_count) {
+                                                                  uint32_t cap, DevEntry* out, uint32_t* out_count,
+                                                                  unsigned char* scratch) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t P0 = extract_cap(k);
-    uint64_t* cc = (uint64_t*)smem;
+    unsigned char* base = G ? scratch : smem;
+    uint32_t* small = (uint32_t*)(G ? smem : smem + extract_big_bytes(k));
+    uint64_t* cc = (uint64_t*)base;
     uint64_t* ce = cc + P0;
     uint32_t* ci = (uint32_t*)(ce + P0);
     const uint32_t tid = threadIdx.x;
@@ -72,16 +83,15 @@ __global__ __launch_bounds__(kExtractThreads) void extract_kernel(WideSummary s,
     if (kind == 0) {
         // reported prefix: count > floor(N / k)
         const uint64_t thr = N / k;
-        __shared__ uint32_t qs;
-        if (tid == 0) qs = 0;
+        if (tid == 0) small[0] = 0;
         __syncthreads();
         for (uint32_t i = tid; i < size; i += kExtractThreads) {
             bool in = cc[i] > thr;
             bool next_out = (i + 1 >= size) || !(cc[i + 1] > thr);
-            if (in && next_out) qs = i + 1;
+            if (in && next_out) small[0] = i + 1;
         }
         __syncthreads();
-        q = qs;
+        q = small[0];
     } else {
         q = size < cap ? size : cap;
     }
@@ -98,11 +108,17 @@ __global__ __launch_bounds__(kExtractThreads) void extract_kernel(WideSummary s,
 }
 
 hipError_t launch_extract(const WideSummary& s, uint32_t k, uint64_t N, int kind, uint32_t cap, DevEntry* out,
-                          uint32_t* out_count, hipStream_t stream) {
-    const uint32_t lds = extract_lds_bytes(k);
-    hipFuncSetAttribute((const void*)extract_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(extract_kernel, dim3(1), dim3(kExtractThreads), lds, stream, s, k, N, kind, cap, out,
-                       out_count);
+                          uint32_t* out_count, bool in_lds, unsigned char* scratch, hipStream_t stream) {
+    const uint32_t bytes = extract_lds_bytes(k);
+    if (in_lds) {
+        hipFuncSetAttribute((const void*)extract_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        hipLaunchKernelGGL(extract_kernel<false>, dim3(1), dim3(kExtractThreads), bytes, stream, s, k, N, kind, cap,
+                           out, out_count, (unsigned char*)nullptr);
+    } else {
+        if (!scratch) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(extract_kernel<true>, dim3(1), dim3(kExtractThreads), kExtractSmallBytes, stream, s, k, N,
+                           kind, cap, out, out_count, scratch);
+    }
     return hipGetLastError();
 }
 

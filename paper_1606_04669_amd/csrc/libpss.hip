@@ -19,6 +19,15 @@ using namespace pss;
 namespace {
 
 constexpr uint32_t kMaxChunks = 1u << 22;
+// Largest k: the HBM-resident block state indexes counters and hash slots
+// with 32 bits, and the report sorts next_pow2(k) entries in one workgroup.
+constexpr uint32_t kMaxK = 1u << 20;
+// Device memory the HBM-resident block states of one update may take; the
+// planner lowers C below this.
+constexpr size_t kStateBudget = 16ull << 30;
+// Concurrent COMBINE workgroups (one scratch slab each) when a COMBINE's
+// arrays do not fit LDS.
+constexpr uint32_t kCombineSlabsPerCu = 2;
 
 struct DeviceBuffer {
     void* ptr = nullptr;
@@ -59,6 +68,9 @@ struct pss_ctx {
     size_t lds_max = 0;      // dynamic LDS per workgroup
     size_t lds_per_cu = 0;
     DeviceBuffer blocks;     // block summaries of one update
+    DeviceBuffer gstate;     // per-block state when it does not fit LDS
+    DeviceBuffer cscratch;   // COMBINE level slabs when they do not fit LDS
+    DeviceBuffer wscratch;   // fold / merge / report arrays when they do not fit LDS
     DeviceBuffer query;      // report buffer
     void* pinned = nullptr;  // host staging for reports
     size_t pinned_bytes = 0;
@@ -127,13 +139,36 @@ WideSummary carve_summary(void* base, uint32_t k) {
     return v;
 }
 
-bool k_fits(const pss_ctx* ctx, uint32_t k) {
-    if (k < 2) return false;
-    return chunk_summary_lds_bytes(k) <= ctx->lds_max && combine_lds_bytes(k, true) <= ctx->lds_max &&
-           extract_lds_bytes(k) <= ctx->lds_max;
-}
+bool k_fits(const pss_ctx*, uint32_t k) { return k >= 2 && k <= kMaxK; }
 
 int check(hipError_t e) { return e == hipSuccess ? PSS_OK : PSS_EDEVICE; }
+
+// Where the arrays of each kernel live for k counters on this device.
+struct KPlan {
+    ChunkLayout L;
+    bool comb_lds;  // block-tree COMBINE (32-bit counts)
+    bool wide_lds;  // fold / merge (64-bit counts)
+    bool ext_lds;   // report sort
+};
+
+KPlan kplan(const pss_ctx* ctx, uint32_t k) {
+    KPlan p;
+    p.L = chunk_layout(k, ctx->lds_max);
+    p.comb_lds = combine_lds_bytes(k, false) <= ctx->lds_max;
+    p.wide_lds = combine_lds_bytes(k, true) <= ctx->lds_max;
+    p.ext_lds = extract_lds_bytes(k) <= ctx->lds_max;
+    return p;
+}
+
+uint32_t combine_slabs(const pss_ctx* ctx) { return (uint32_t)std::max(1, ctx->cu_count) * kCombineSlabsPerCu; }
+
+// Scratch of fold, merge and report (stream-ordered, so one buffer serves all).
+int ensure_wscratch(pss_ctx* ctx, const KPlan& p, uint32_t k) {
+    size_t need = 0;
+    if (!p.wide_lds) need = std::max(need, combine_scratch_bytes(k, true));
+    if (!p.ext_lds) need = std::max(need, extract_scratch_bytes(k));
+    return need ? ctx->wscratch.grow(need) : PSS_OK;
+}
 
 hipEvent_t take_event(pss_ctx* ctx) {
     if (!ctx->event_pool.empty()) {
@@ -173,12 +208,19 @@ void close_phase(pss_ctx* ctx, int phase, hipEvent_t a, hipStream_t st) {
 }
 
 // block summaries of d_items[0, n) into the context workspace
-int run_blocks(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks, hipStream_t st,
+int run_blocks(pss_ctx* ctx, const KPlan& p, const uint32_t* d_items, uint64_t n, uint32_t chunks, hipStream_t st,
                BlockSummaries* out) {
+    const uint32_t k = p.L.k;
     int rc = ctx->blocks.grow(blocks_bytes(chunks, k));
     if (rc != PSS_OK) return rc;
+    unsigned char* gs = nullptr;
+    if (p.L.global_state) {
+        rc = ctx->gstate.grow((size_t)chunks * p.L.state_bytes);
+        if (rc != PSS_OK) return rc;
+        gs = (unsigned char*)ctx->gstate.ptr;
+    }
     *out = carve_blocks(ctx->blocks.ptr, chunks, k);
-    return check(launch_chunk_summary(d_items, n, chunks, k, *out, st));
+    return check(launch_chunk_summary(d_items, n, chunks, p.L, *out, gs, st));
 }
 
 int ensure_pinned(pss_ctx* ctx, size_t bytes) {
@@ -273,32 +315,41 @@ void pss_ctx_destroy(pss_ctx* ctx) {
     pss_phase_times(ctx, nullptr, nullptr, 1);
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     ctx->blocks.release();
+    ctx->gstate.release();
+    ctx->cscratch.release();
+    ctx->wscratch.release();
     ctx->query.release();
     if (ctx->pinned) hipHostFree(ctx->pinned);
     delete ctx;
 }
 
-uint32_t pss_max_k(const pss_ctx* ctx) {
+uint32_t pss_max_k(const pss_ctx* ctx) { return ctx ? kMaxK : 0; }
+
+uint32_t pss_max_lds_k(const pss_ctx* ctx) {
     if (!ctx) return 0;
-    uint32_t lo = 2, hi = 1u << 20;
-    if (!k_fits(ctx, lo)) return 0;
+    // the LDS-resident layout grows with k, so the largest fitting k is found by bisection
+    uint32_t lo = 2, hi = kMaxK;
+    if (chunk_layout(lo, ctx->lds_max).global_state) return 0;
     while (lo < hi) {
         uint32_t mid = lo + (hi - lo + 1) / 2;
-        if (k_fits(ctx, mid)) lo = mid; else hi = mid - 1;
+        if (!chunk_layout(mid, ctx->lds_max).global_state) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
 
 uint32_t pss_plan_chunks(const pss_ctx* ctx, uint64_t n, uint32_t k) {
     if (!ctx || n == 0 || k < 2) return 1;
+    if (k > kMaxK) k = kMaxK;
     // enough resident waves to cover every CU a few times over, while keeping
     // blocks long next to k (the reduction tree moves ~C*k entries)
-    uint64_t per_cu = ctx->lds_per_cu / std::max<uint32_t>(1, chunk_summary_lds_bytes(k));
-    if (per_cu < 1) per_cu = 1;
+    const ChunkLayout L = chunk_layout(k, ctx->lds_max);
+    uint64_t per_cu = ctx->lds_per_cu / std::max<uint32_t>(1, L.lds_bytes);
+    per_cu = std::min<uint64_t>(std::max<uint64_t>(per_cu, 1), 32);  // 32 waves per CU at most
     uint64_t want = (uint64_t)ctx->cu_count * per_cu * 4;
     uint64_t cap_len = n / (16ull * k);
     if (cap_len < 1) cap_len = 1;
     uint64_t c = std::min(want, cap_len);
+    if (L.global_state) c = std::min<uint64_t>(c, kStateBudget / L.state_bytes);
     c = std::min<uint64_t>(c, kMaxChunks);
     return (uint32_t)std::max<uint64_t>(c, 1);
 }
@@ -350,22 +401,30 @@ int pss_update(pss_summary* s, const uint32_t* d_items, uint64_t n, uint32_t chu
     if (C > kMaxChunks) return PSS_ERANGE;
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    BlockSummaries b;
-    int rc = ctx->blocks.grow(blocks_bytes(C, k));
+    const KPlan kp = kplan(ctx, k);
+    int rc = ensure_wscratch(ctx, kp, k);
     if (rc != PSS_OK) return rc;
-    b = carve_blocks(ctx->blocks.ptr, C, k);
+    unsigned char* cs = nullptr;
+    uint32_t slabs = 0;
+    if (!kp.comb_lds && C > 1) {
+        slabs = std::min(combine_slabs(ctx), C / 2);
+        rc = ctx->cscratch.grow((size_t)slabs * combine_scratch_bytes(k, false));
+        if (rc != PSS_OK) return rc;
+        cs = (unsigned char*)ctx->cscratch.ptr;
+    }
+    BlockSummaries b;
     hipEvent_t t0 = mark(ctx, st);
-    rc = check(launch_chunk_summary(d_items, n, C, k, b, st));
+    rc = run_blocks(ctx, kp, d_items, n, C, st, &b);
     if (rc != PSS_OK) return rc;
     close_phase(ctx, 0, t0, st);
     hipEvent_t t1 = mark(ctx, st);
     for (uint32_t step = 1; step < C; step <<= 1) {
-        rc = check(launch_combine_level(b, k, C, step, st));
+        rc = check(launch_combine_level(b, k, C, step, kp.comb_lds, cs, slabs, st));
         if (rc != PSS_OK) return rc;
     }
     close_phase(ctx, 1, t1, st);
     hipEvent_t t2 = mark(ctx, st);
-    rc = check(launch_fold(s->view, b, k, st));
+    rc = check(launch_fold(s->view, b, k, kp.wide_lds, (unsigned char*)ctx->wscratch.ptr, st));
     if (rc != PSS_OK) return rc;
     close_phase(ctx, 2, t2, st);
     s->n += n;
@@ -376,8 +435,13 @@ int pss_update(pss_summary* s, const uint32_t* d_items, uint64_t n, uint32_t chu
 int pss_merge(pss_summary* dst, const pss_summary* src, void* stream) {
     if (!dst || !src || dst == src) return PSS_EINVAL;
     if (dst->k != src->k || dst->ctx->device != src->ctx->device) return PSS_EINVAL;
-    DeviceGuard g(dst->ctx->device);
-    int rc = check(launch_merge(dst->view, src->view, dst->k, (hipStream_t)stream));
+    pss_ctx* ctx = dst->ctx;
+    DeviceGuard g(ctx->device);
+    const KPlan kp = kplan(ctx, dst->k);
+    int rc = ensure_wscratch(ctx, kp, dst->k);
+    if (rc != PSS_OK) return rc;
+    rc = check(launch_merge(dst->view, src->view, dst->k, kp.wide_lds, (unsigned char*)ctx->wscratch.ptr,
+                            (hipStream_t)stream));
     if (rc != PSS_OK) return rc;
     dst->n += src->n;
     return PSS_OK;
@@ -393,7 +457,10 @@ int pss_query(const pss_summary* s, int kind, pss_entry* h_out, uint32_t cap, ui
     hipStream_t st = (hipStream_t)stream;
     const size_t ebytes = (size_t)k * sizeof(DevEntry);
     const size_t qbytes = 256 + ebytes;
-    int rc = ctx->query.grow(qbytes);
+    const KPlan kp = kplan(ctx, k);
+    int rc = ensure_wscratch(ctx, kp, k);
+    if (rc != PSS_OK) return rc;
+    rc = ctx->query.grow(qbytes);
     if (rc != PSS_OK) return rc;
     rc = ensure_pinned(ctx, qbytes);
     if (rc != PSS_OK) return rc;
@@ -401,7 +468,8 @@ int pss_query(const pss_summary* s, int kind, pss_entry* h_out, uint32_t cap, ui
     DevEntry* d_ent = (DevEntry*)((char*)ctx->query.ptr + 256);
     const uint32_t dev_cap = kind == PSS_Q_TOPK ? std::min(cap, k) : k;
     hipEvent_t t3 = mark(ctx, st);
-    rc = check(launch_extract(s->view, k, s->n, kind, dev_cap, d_ent, d_count, st));
+    rc = check(launch_extract(s->view, k, s->n, kind, dev_cap, d_ent, d_count, kp.ext_lds,
+                              (unsigned char*)ctx->wscratch.ptr, st));
     if (rc != PSS_OK) return rc;
     if (hipMemcpyAsync(ctx->pinned, ctx->query.ptr, qbytes, hipMemcpyDeviceToHost, st) != hipSuccess)
         return PSS_EDEVICE;
@@ -458,7 +526,7 @@ int pss_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint3
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
     BlockSummaries b;
-    int rc = run_blocks(ctx, d_items, n, k, chunks, st, &b);
+    int rc = run_blocks(ctx, kplan(ctx, k), d_items, n, chunks, st, &b);
     if (rc != PSS_OK) return rc;
     if (hipStreamSynchronize(st) != hipSuccess) return PSS_EDEVICE;
     for (uint32_t i = 0; i < nsel; ++i) {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pss_layout.h"
+
 namespace pss {
 
 // A set of summaries stored at stride k (entries of summary p start at p*k),
@@ -28,26 +30,38 @@ struct DevEntry {
     uint64_t error;
 };
 
-hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t chunks, uint32_t k,
-                                const BlockSummaries& out, hipStream_t stream);
-uint32_t chunk_summary_lds_bytes(uint32_t k);
+// Layout of one block summary for k counters: state in LDS when it fits in
+// lds_max bytes (with 16-bit indices), else in a global slab per block.
+ChunkLayout chunk_layout(uint32_t k, size_t lds_max);
+// gstate: chunks * L.state_bytes bytes of device memory when L.global_state.
+hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L,
+                                const BlockSummaries& out, unsigned char* gstate, hipStream_t stream);
 
 // One level of the fixed tree over `count` block summaries: node j combines
 // summaries 2*step*j and 2*step*j + step into position 2*step*j.
-hipError_t launch_combine_level(const BlockSummaries& v, uint32_t k, uint32_t count, uint32_t step,
-                                hipStream_t stream);
+// in_lds: the O(k) arrays of a COMBINE fit LDS (combine_lds_bytes <= limit);
+// otherwise scratch holds `slabs` slabs of combine_scratch_bytes and at most
+// that many workgroups run, each merging several pairs in turn.
+hipError_t launch_combine_level(const BlockSummaries& v, uint32_t k, uint32_t count, uint32_t step, bool in_lds,
+                                unsigned char* scratch, uint32_t slabs, hipStream_t stream);
 // dst <- COMBINE(dst, src) for a narrow (block/tree) src at position 0.
-hipError_t launch_fold(const WideSummary& dst, const BlockSummaries& src, uint32_t k, hipStream_t stream);
+hipError_t launch_fold(const WideSummary& dst, const BlockSummaries& src, uint32_t k, bool in_lds,
+                       unsigned char* scratch, hipStream_t stream);
 // dst <- COMBINE(dst, src) for two wide summaries.
-hipError_t launch_merge(const WideSummary& dst, const WideSummary& src, uint32_t k, hipStream_t stream);
+hipError_t launch_merge(const WideSummary& dst, const WideSummary& src, uint32_t k, bool in_lds,
+                        unsigned char* scratch, hipStream_t stream);
 uint32_t combine_lds_bytes(uint32_t k, bool wide);
+size_t combine_scratch_bytes(uint32_t k, bool wide);
 
 // Canonically ordered report of a wide summary: kind 0 = count*k > N,
 // kind 1 = first `cap`.  Writes entries to out and the reported count
 // (before truncation to cap for kind 0) to *out_count.
+// in_lds: the sort arrays fit LDS (extract_lds_bytes <= limit); otherwise
+// scratch holds extract_scratch_bytes bytes.
 hipError_t launch_extract(const WideSummary& s, uint32_t k, uint64_t N, int kind, uint32_t cap, DevEntry* out,
-                          uint32_t* out_count, hipStream_t stream);
+                          uint32_t* out_count, bool in_lds, unsigned char* scratch, hipStream_t stream);
 uint32_t extract_lds_bytes(uint32_t k);
+size_t extract_scratch_bytes(uint32_t k);
 
 // Set a wide summary to the empty summary.
 hipError_t launch_reset(const WideSummary& s, hipStream_t stream);

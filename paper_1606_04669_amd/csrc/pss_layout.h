@@ -1,5 +1,8 @@
-// LDS layout of one block summary, shared by the host launcher and the
-// chunk_summary kernel.  One wave owns one layout.
+// Memory layout of one block summary, shared by the host launcher and the
+// chunk_summary kernel.  One wave owns one layout.  The per-block state (hash
+// table, counters, minimum-level list) lives in LDS when it fits, otherwise in
+// a global-memory slab of state_bytes per block; the input ring and a few
+// small per-window arrays always live in LDS.
 #pragma once
 
 #include <stdint.h>
@@ -15,8 +18,8 @@ namespace pss {
 // Items staged per half of the LDS input ring (two halves).
 constexpr uint32_t kRingHalf = 512;
 constexpr uint32_t kRing = 2 * kRingHalf;
-// Largest hash table (slot positions are stored as uint16).
-constexpr uint32_t kMaxTableSlots = 65536;
+// Largest hash table whose slot positions fit uint16 (LDS-resident state).
+constexpr uint32_t kMaxLdsTableSlots = 65536;
 
 PSS_HD inline uint32_t next_pow2(uint32_t v) {
     uint32_t p = 1;
@@ -30,52 +33,68 @@ PSS_HD inline uint32_t log2_pow2(uint32_t p) {
     return b;
 }
 
-// Registers per lane the victim-list sort needs for k counters.
+PSS_HD inline uint32_t align16(uint32_t v) { return (v + 15u) & ~15u; }
+
+// Registers per lane the in-register level sort needs for k counters.
 PSS_HD inline uint32_t sort_lanes_per_k(uint32_t k) {
     return next_pow2((k + 63) / 64);
 }
 
 struct ChunkLayout {
     uint32_t k;
-    uint32_t nbuckets;  // hash buckets of 4 slots
-    uint32_t tsize;     // 4 * nbuckets slots
-    // byte offsets inside the wave's LDS block
-    uint32_t off_table, off_cnt, off_item, off_err, off_hpos, off_list, off_mark, off_ring, off_scratch, off_tkey,
-        off_hist;
-    uint32_t bytes;
+    uint32_t nbuckets;      // hash buckets of 4 slots
+    uint32_t tsize;         // 4 * nbuckets slots
+    uint32_t global_state;  // 1: state in global memory, 32-bit indices; 0: LDS, 16-bit indices
+    // state offsets (bytes from the state base)
+    uint32_t off_table, off_cnt, off_item, off_err, off_hpos, off_list, off_mark, off_tkey, off_list2, off_tkey2;
+    uint32_t state_bytes;
+    // LDS offsets (bytes from the LDS base; the state comes first when it is in LDS)
+    uint32_t off_ring, off_vslot, off_vhpos, off_hist;
+    uint32_t lds_bytes;
 
     // Default hash slots per counter (x16): more room (shorter probes, fewer
-    // rebuilds) while the LDS footprint is small, 2 per counter for large k.
+    // rebuilds) while the footprint is small, 2 per counter for large k.
     PSS_HD static uint32_t default_slots_x16(uint32_t k) { return k <= 1024 ? 64 : 32; }
 
-    // slots_per_counter (x16): hash slots per counter; a speed / LDS knob
-    // that never changes results (0 = default_slots_x16).
-    PSS_HD static ChunkLayout make(uint32_t k, uint32_t slots_per_counter_x16 = 0) {
+    // slots_per_counter_x16: hash slots per counter (x16), a speed / memory
+    // knob that never changes results (0 = default).  global_state selects
+    // where the per-block state lives.
+    PSS_HD static ChunkLayout make(uint32_t k, bool global_state, uint32_t slots_per_counter_x16 = 0) {
         ChunkLayout L;
         L.k = k;
+        L.global_state = global_state ? 1u : 0u;
         if (slots_per_counter_x16 == 0) slots_per_counter_x16 = default_slots_x16(k);
-        uint32_t slots = (k * slots_per_counter_x16 + 15) / 16;
+        uint32_t slots = (uint32_t)(((uint64_t)k * slots_per_counter_x16 + 15) / 16);
         if (slots < 256) slots = 256;
         L.nbuckets = (slots + 3) / 4;
         L.tsize = 4 * L.nbuckets;
+        const uint32_t idx = global_state ? 4u : 2u;
         uint32_t o = 0;
-        L.off_table = o;   o += 8 * L.tsize;           // uint64 entries (key | tag << 32), 32 B buckets
-        L.off_cnt = o;     o += 4 * ((k + 3) & ~3u);
-        L.off_item = o;    o += 4 * ((k + 3) & ~3u);
-        L.off_err = o;     o += 4 * ((k + 3) & ~3u);
-        L.off_hpos = o;    o += 2 * ((k + 7) & ~7u);   // uint16 table slot of each counter
-        L.off_list = o;    o += 2 * ((k + 7) & ~7u);   // uint16 counters of the minimum level, by id
-        L.off_mark = o;    o += (k + 15) & ~15u;       // uint8 victim ranks
-        L.off_ring = o;    o += 4 * kRing;             // staged input items
-        L.off_scratch = o; o += 4 * 64;                // victim slot | table slot << 16, per rank
-        L.off_tkey = o;    o += 4 * ((k + 3) & ~3u);   // ids in bucket order while a level is sorted
-        L.off_hist = o;    o += 4 * 257;               // bucket counts / starts while a level is sorted
-        o = (o + 15) & ~15u;
-        L.bytes = o;
+        L.off_table = o; o = align16(o + 8 * L.tsize);   // uint64 entries (key | tag << 32), 32 B buckets
+        L.off_cnt = o;   o = align16(o + 4 * k);
+        L.off_item = o;  o = align16(o + 4 * k);
+        L.off_err = o;   o = align16(o + 4 * k);
+        L.off_hpos = o;  o = align16(o + idx * k);       // table slot of each counter
+        L.off_list = o;  o = align16(o + idx * k);       // counters of the minimum level, by id
+        L.off_mark = o;  o = align16(o + k);             // uint8 victim ranks
+        L.off_tkey = o;  o = align16(o + 4 * k);         // ids while a level is sorted
+        L.off_list2 = o;
+        L.off_tkey2 = o;
+        if (global_state) {                              // ping-pong buffers of the radix sort
+            L.off_list2 = o; o = align16(o + 4 * k);
+            L.off_tkey2 = o; o = align16(o + 4 * k);
+        }
+        L.state_bytes = o;
+        uint32_t l = global_state ? 0u : o;
+        L.off_ring = l;  l = align16(l + 4 * kRing);     // staged input items
+        L.off_vslot = l; l = align16(l + 4 * 64);        // victim counter per rank
+        L.off_vhpos = l; l = align16(l + 4 * 64);        // its table slot
+        L.off_hist = l;  l = align16(l + 4 * 257);       // bucket counts / starts while a level is sorted
+        L.lds_bytes = l;
         return L;
     }
 
-    PSS_HD bool valid() const { return tsize <= kMaxTableSlots; }
+    PSS_HD bool fits_lds_indices() const { return tsize <= kMaxLdsTableSlots && k <= 65535u; }
 };
 
 }  // namespace pss

@@ -75,3 +75,14 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src and "pss_oracle" not in src, f
+
+
+def test_kernels_take_all_lds_dynamically():
+    # the host sizes every launch's LDS from the dynamic byte counts it passes,
+    # so no kernel may add static shared arrays on top of them
+    import glob
+    csrc = os.path.join(ROOT, "paper_1606_04669_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        for line in open(f).read().splitlines():
+            if "__shared__" in line and not line.lstrip().startswith("//"):
+                assert re.search(r"extern\s+__shared__", line), (f, line)

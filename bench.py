@@ -21,10 +21,53 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "G items/s + % HBM-read roofline (1 GPU); batched/served vs plain; p99 latency"
+# HBM traffic of the block kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# valid only while the kernel source is the one the counters were taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chunk_summary_plain_large_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1606_04669_amd", "csrc", "chunk_summary.hip")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in (KERNEL_SOURCE, os.path.join(os.path.dirname(KERNEL_SOURCE), "pss_layout.h"),
+              os.path.join(os.path.dirname(KERNEL_SOURCE), "pss_device.h")):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, n_log2: int):
+    """Bytes per block-kernel launch from the committed counter runs, or None
+    when they were taken on another kernel source or workload."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    if t.get("workload") != workload or t.get("n_log2") != n_log2:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def copy_calibration(log2_elems: int = 28, reps: int = 3):
+    """A plain elementwise kernel of known traffic (reads and writes 4 B per
+    element) for scaling the HBM byte counters."""
+    import torch
+    src = torch.arange(1 << log2_elems, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.bitwise_not(src, out=dst)
+    torch.cuda.synchronize()
+    log("copy calibration: %d launches of bitwise_not over 2^%d int32 (%d bytes read, %d written per launch)"
+        % (reps, log2_elems, 4 << log2_elems, 4 << log2_elems))
 
 
 def workload_cases(name: str, n_log2: int, seed: int):
@@ -37,6 +80,8 @@ def workload_cases(name: str, n_log2: int, seed: int):
         return streams, ks
     if name == "plain":
         return [W.plain(seed, n)], [100]
+    if name == "plain-highk":
+        return [W.plain_highk(seed, n), W.plain_highk_adversarial(seed, n)], [10000, 50000]
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -68,23 +113,28 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="plain-large", choices=["plain-large", "plain"])
+    ap.add_argument("--workload", default="plain-large", choices=["plain-large", "plain", "plain-highk"])
     ap.add_argument("--n-log2", type=int, default=None)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=24)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain elementwise kernel of known traffic (for counter runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding)",
               file=sys.stderr)
         sys.exit(2)
-    n_log2 = args.n_log2 if args.n_log2 is not None else (30 if args.workload == "plain-large" else 20)
+    n_log2 = args.n_log2 if args.n_log2 is not None else {"plain-large": 30, "plain": 20, "plain-highk": 31}[
+        args.workload]
 
     import numpy as np
     import torch
     from paper_1606_04669_amd import binding as B
 
+    if args.copy_calibration:
+        copy_calibration()
     streams, ks = workload_cases(args.workload, n_log2, args.seed)
     host, dev = [], []
     for st in streams:
@@ -140,7 +190,7 @@ def main():
                           "ms_median": round(med, 3), "g_items_per_s": round(n_items / med / 1e6, 2)})
     total_ms = sum(ms)
     result = {
-        "metric": "G items/s (plain single-stream Parallel Space Saving, 1 GPU)",
+        "metric": METRIC,
         "value": round(value, 3),
         "unit": "G items/s",
         "n_gpus": 1,
@@ -165,7 +215,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, n_log2),
             "avg_launch_ms": round(cs_avg_ms, 4),
             "launches": launches[0],
         },

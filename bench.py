@@ -123,7 +123,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     n_log2 = args.n_log2 if args.n_log2 is not None else {"plain-large": 30, "plain": 20, "plain-highk": 31}[

@@ -140,7 +140,7 @@ def zipf_ranks(n: int, alpha: float, n_univ: int, key: int) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
-# Workload recipes (shapes of the paper's experiments)
+# Workload recipes (shapes of the paper's experiments: Zipf skew, long streams, k in the thousands)
 # ----------------------------------------------------------------------------
 
 @dataclass(frozen=True)

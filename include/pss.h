@@ -142,6 +142,56 @@ int pss_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint3
                         const uint32_t* h_sel, uint32_t nsel, pss_entry* h_out, uint32_t* h_sizes,
                         uint64_t* h_mins, void* stream);
 
+/* ---- Batched form: many independent streams in one graph launch ----
+ *
+ * Stream s is the device array h_items[s][0, h_lens[s]) with k = h_ks[s]
+ * counters; its result is exactly that of pss_run on it with
+ * C = h_chunks[s] (Algorithm 1 with Algorithm 2 as the reduction): the batch
+ * changes scheduling only.  Requires 2 <= k_s <= n_s, n_s < 2^32 and
+ * k_s <= pss_batch_max_k() (PSS_ERANGE otherwise). */
+typedef struct pss_batch pss_batch;
+
+typedef struct {
+    uint32_t nstreams, nblocks, nlevels, nclasses;
+    uint64_t target_len;      /* tuned block length (items) */
+    uint32_t slots_x16;       /* tuned hash slots per counter x16 (0 = per-k default) */
+    uint32_t waves_per_group; /* tuned waves per workgroup of the block kernels */
+    uint32_t tune_candidates; /* configurations the autotuner timed */
+    double tune_ms;           /* time spent tuning */
+    uint64_t report_entries;  /* sum of k_s: size of h_out in pss_batch_run */
+} pss_batch_info_t;
+
+/* Largest k a batched stream may have on this context (block state and a
+ * COMBINE both in LDS). */
+uint32_t pss_batch_max_k(const pss_ctx* ctx);
+
+/* Plan a batch.  h_items (host array of nstreams device pointers, each to be
+ * kept valid for the life of the batch), h_lens, h_ks: the streams.
+ * h_chunks[s]: C_s, or 0 to let the autotuner choose it; on success every
+ * entry holds the C_s used (record them to reproduce results).  tune != 0
+ * also tunes the result-neutral knobs when every C_s is given.  The
+ * autotuner times candidate configurations (block length, hash load factor,
+ * waves per workgroup) on a sample of the streams; the chosen launch
+ * sequence is captured into a HIP graph. */
+int pss_batch_create(pss_ctx* ctx, uint32_t nstreams, const uint32_t* const* h_items, const uint64_t* h_lens,
+                     const uint32_t* h_ks, uint32_t* h_chunks, int tune, pss_batch** out);
+
+/* Run a batch (graph replay, or eager launches when eager != 0) on `stream`
+ * and wait for it.  Stream s's reported entries (count * k_s > n_s, canonical
+ * order) go to h_out[o_s ...] with o_s = k_0 + ... + k_{s-1}; their number
+ * to h_counts[s].  h_out holds report_entries entries. */
+int pss_batch_run(pss_batch* b, int eager, pss_entry* h_out, uint32_t* h_counts, void* stream);
+
+/* The plan's shape and tuning. */
+int pss_batch_info(const pss_batch* b, pss_batch_info_t* info);
+
+/* Release a batch (waits for the device).  NULL is accepted. */
+void pss_batch_destroy(pss_batch* b);
+
+/* create + run + destroy in one call (no tuning of given C_s). */
+int pss_run_batched(pss_ctx* ctx, uint32_t nstreams, const uint32_t* const* h_items, const uint64_t* h_lens,
+                    const uint32_t* h_ks, uint32_t* h_chunks, pss_entry* h_out, uint32_t* h_counts, void* stream);
+
 /* Phase timing.  While enabled, pss_update, pss_run and pss_query record HIP
  * events on the call's stream around each phase: 0 = block summaries
  * (chunk_summary kernel), 1 = COMBINE tree, 2 = fold into the summary,

@@ -23,6 +23,17 @@ PSS_Q_MAJORITY, PSS_Q_TOPK = 0, 1
 ENTRY_DTYPE = np.dtype([("item", "<u4"), ("reserved", "<u4"), ("count", "<u8"), ("error", "<u8")])
 
 
+class BatchInfo(ctypes.Structure):
+    """pss_batch_info_t"""
+    _fields_ = [("nstreams", ctypes.c_uint32), ("nblocks", ctypes.c_uint32), ("nlevels", ctypes.c_uint32),
+                ("nclasses", ctypes.c_uint32), ("target_len", ctypes.c_uint64), ("slots_x16", ctypes.c_uint32),
+                ("waves_per_group", ctypes.c_uint32), ("tune_candidates", ctypes.c_uint32),
+                ("tune_ms", ctypes.c_double), ("report_entries", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class PssError(RuntimeError):
     def __init__(self, code: int, what: str, required: int | None = None):
         self.code = code
@@ -60,10 +71,19 @@ def lib():
         L.pss_query.argtypes = [vp, i32, vp, u32, u32p, u64p, vp]
         L.pss_run.argtypes = [vp, vp, u64, u32, u32, vp, u32, u32p, u32p, vp]
         L.pss_block_summaries.argtypes = [vp, vp, u64, u32, u32, u32p, u32, vp, u32p, u64p, vp]
+        L.pss_batch_max_k.restype = u32
+        L.pss_batch_max_k.argtypes = [vp]
+        L.pss_batch_create.argtypes = [vp, u32, vp, u64p, u32p, u32p, i32, ctypes.POINTER(vp)]
+        L.pss_batch_run.argtypes = [vp, i32, vp, u32p, vp]
+        L.pss_batch_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+        L.pss_batch_destroy.argtypes = [vp]
+        L.pss_batch_destroy.restype = None
+        L.pss_run_batched.argtypes = [vp, u32, vp, u64p, u32p, u32p, vp, u32p, vp]
         L.pss_timing_enable.argtypes = [vp, i32]
         L.pss_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), u32p, i32]
-        for f in ("pss_timing_enable", "pss_phase_times", "pss_ctx_create", "pss_create", "pss_update", "pss_merge", "pss_query", "pss_run",
-                  "pss_block_summaries"):
+        for f in ("pss_timing_enable", "pss_phase_times", "pss_ctx_create", "pss_create", "pss_update", "pss_merge",
+                  "pss_query", "pss_run", "pss_block_summaries", "pss_batch_create", "pss_batch_run", "pss_batch_info",
+                  "pss_run_batched"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -121,6 +141,10 @@ class Context:
     @property
     def max_lds_k(self) -> int:
         return int(lib().pss_max_lds_k(self.handle))
+
+    @property
+    def batch_max_k(self) -> int:
+        return int(lib().pss_batch_max_k(self.handle))
 
     def plan_chunks(self, n: int, k: int) -> int:
         return int(lib().pss_plan_chunks(self.handle, n, k))
@@ -227,6 +251,101 @@ def pss_block_summaries(ctx: Context, d_items, k: int, chunks: int, sel, stream=
                                    ctypes.c_void_p(_stream(stream)))
     _check(rc, "pss_block_summaries")
     return [(out[i * k: i * k + int(sizes[i])].copy(), int(mins[i])) for i in range(len(sel))]
+
+
+def _batch_arrays(streams, ks, chunks):
+    ptrs, lens = [], []
+    for d in streams:
+        p, n = _items(d)
+        ptrs.append(p.value)
+        lens.append(n)
+    ns = len(ptrs)
+    if len(ks) != ns:
+        raise ValueError("one k per stream")
+    a_ptr = (ctypes.c_void_p * ns)(*ptrs)
+    a_len = np.ascontiguousarray(np.asarray(lens, dtype=np.uint64))
+    a_k = np.ascontiguousarray(np.asarray(ks, dtype=np.uint32))
+    a_c = np.ascontiguousarray(np.zeros(ns, dtype=np.uint32) if chunks is None else np.asarray(chunks, dtype=np.uint32))
+    return ns, a_ptr, a_len, a_k, a_c
+
+
+def _split_reports(out, counts, ks):
+    res, o = [], 0
+    for s, k in enumerate(ks):
+        res.append(out[o: o + int(counts[s])].copy())
+        o += int(k)
+    return res
+
+
+class Batch:
+    """pss_batch: the streams (device tensors, kept referenced for the life of
+    the batch), their k and, optionally, their chunk counts (None or 0 entries:
+    chosen by the autotuner)."""
+
+    def __init__(self, ctx: Context, streams, ks, chunks=None, tune: bool = False):
+        self.streams = list(streams)
+        ns, a_ptr, a_len, a_k, a_c = _batch_arrays(self.streams, ks, chunks)
+        h = ctypes.c_void_p()
+        _check(lib().pss_batch_create(ctx.handle, ns, a_ptr, a_len.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                      a_k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                      a_c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), 1 if tune else 0,
+                                      ctypes.byref(h)), "pss_batch_create")
+        self.handle = h
+        self.ctx = ctx
+        self.ks = [int(k) for k in a_k]
+        self.chunks = [int(c) for c in a_c]
+        self._out = np.zeros(max(1, int(a_k.sum(dtype=np.uint64))), dtype=ENTRY_DTYPE)
+        self._counts = np.zeros(ns, dtype=np.uint32)
+
+    def run(self, eager: bool = False, stream=None):
+        """Per-stream reported entries (list of ENTRY_DTYPE arrays)."""
+        _check(lib().pss_batch_run(self.handle, 1 if eager else 0, self._out.ctypes.data_as(ctypes.c_void_p),
+                                   self._counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                   ctypes.c_void_p(_stream(stream))), "pss_batch_run")
+        return _split_reports(self._out, self._counts, self.ks)
+
+    def info(self) -> dict:
+        i = BatchInfo()
+        _check(lib().pss_batch_info(self.handle, ctypes.byref(i)), "pss_batch_info")
+        return i.as_dict()
+
+    def close(self):
+        if self.handle:
+            lib().pss_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pss_batch_create(ctx: Context, streams, ks, chunks=None, tune: bool = False) -> Batch:
+    return Batch(ctx, streams, ks, chunks, tune)
+
+
+def pss_batch_run(b: Batch, eager: bool = False, stream=None):
+    return b.run(eager, stream)
+
+
+def pss_batch_destroy(b: Batch):
+    b.close()
+
+
+def pss_run_batched(ctx: Context, streams, ks, chunks=None, stream=None):
+    """One-shot batch: (per-stream reports, chunk counts used)."""
+    streams = list(streams)
+    ns, a_ptr, a_len, a_k, a_c = _batch_arrays(streams, ks, chunks)
+    out = np.zeros(max(1, int(a_k.sum(dtype=np.uint64))), dtype=ENTRY_DTYPE)
+    counts = np.zeros(ns, dtype=np.uint32)
+    _check(lib().pss_run_batched(ctx.handle, ns, a_ptr, a_len.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                 a_k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                 a_c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                 out.ctypes.data_as(ctypes.c_void_p),
+                                 counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                 ctypes.c_void_p(_stream(stream))), "pss_run_batched")
+    return _split_reports(out, counts, [int(k) for k in a_k]), [int(c) for c in a_c]
 
 
 def to_tuples(entries):

@@ -386,31 +386,23 @@ __device__ __forceinline__ void store_half(uint32_t* ring, uint64_t tile, const 
 // The kernel
 // ---------------------------------------------------------------------------
 
+// Space Saving over items[begin, end) by one wave (n bounds every load).
 // P: registers per lane for the in-register level sort (LDS-resident state);
-// G: the per-block state lives in global memory (slab gstate + c * state_bytes)
-// with 32-bit indices, for k whose state does not fit LDS.
+// G: the state at sb lives in global memory with 32-bit indices (k whose
+// state does not fit LDS), else sb is in LDS.  lds holds the input ring and
+// the per-window arrays.  Writes entries [0, size) to o_item/o_cnt/o_err and
+// the header to *o_size, *o_min.
 template <int P, bool G>
-__global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __restrict__ items, uint64_t n,
-                                                           uint32_t chunks, ChunkLayout L, int vec_ok,
-                                                           uint32_t* __restrict__ o_item,
-                                                           uint32_t* __restrict__ o_cnt,
-                                                           uint32_t* __restrict__ o_err,
-                                                           uint32_t* __restrict__ o_size,
-                                                           uint32_t* __restrict__ o_min,
-                                                           unsigned char* __restrict__ gstate) {
+__device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ items, uint64_t n, uint64_t begin,
+                                                uint64_t end, const ChunkLayout& L, int vec_ok, unsigned char* sb,
+                                                unsigned char* lds, uint32_t* __restrict__ o_item,
+                                                uint32_t* __restrict__ o_cnt, uint32_t* __restrict__ o_err,
+                                                uint32_t* __restrict__ o_size, uint32_t* __restrict__ o_min) {
     using idx_t = typename std::conditional<G, uint32_t, uint16_t>::type;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const uint32_t lane = threadIdx.x;
-    const uint32_t c = blockIdx.x;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t k = L.k;
     const uint32_t T = L.tsize;
     const uint32_t NB = L.nbuckets;
-    unsigned char* sb;
-    if constexpr (G) {
-        sb = gstate + (size_t)c * L.state_bytes;
-    } else {
-        sb = smem;
-    }
     uint64_t* table = (uint64_t*)(sb + L.off_table);
     const uint4* tbl4 = (const uint4*)(sb + L.off_table);
     uint32_t* cnt = (uint32_t*)(sb + L.off_cnt);
@@ -422,14 +414,10 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
     uint32_t* tkey = (uint32_t*)(sb + L.off_tkey);
     idx_t* list2 = (idx_t*)(sb + L.off_list2);
     uint32_t* tkey2 = (uint32_t*)(sb + L.off_tkey2);
-    uint32_t* ring = (uint32_t*)(smem + L.off_ring);
-    uint32_t* vslot = (uint32_t*)(smem + L.off_vslot);
-    uint32_t* vhpos = (uint32_t*)(smem + L.off_vhpos);
-    uint32_t* hist = (uint32_t*)(smem + L.off_hist);
-
-    // block bounds (Algorithm 1): [floor(c n / C), floor((c+1) n / C)), n < 2^32
-    const uint64_t begin = (uint64_t)c * n / chunks;
-    const uint64_t end = (uint64_t)(c + 1) * n / chunks;
+    uint32_t* ring = (uint32_t*)(lds + L.off_ring);
+    uint32_t* vslot = (uint32_t*)(lds + L.off_vslot);
+    uint32_t* vhpos = (uint32_t*)(lds + L.off_vhpos);
+    uint32_t* hist = (uint32_t*)(lds + L.off_hist);
     // rebuild the hash when live + tombstone slots pass 3/4 (always >= 65 empty)
     const uint32_t tlimit = min(T - T / 4, T - 65);
 
@@ -749,8 +737,8 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
     wave_sync();
     if (failed) {
         if (lane == 0) {
-            o_size[c] = kBlockFailed;
-            o_min[c] = 0;
+            *o_size = kBlockFailed;
+            *o_min = 0;
         }
         return;
     }
@@ -760,15 +748,108 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
         for (uint32_t s = lane; s < k; s += kWave) mn = min(mn, cnt[s]);
         mo = wave_min_u32(mn);
     }
-    const uint64_t ob = (uint64_t)c * k;
     for (uint32_t s = lane; s < size; s += kWave) {
-        o_item[ob + s] = item[s];
-        o_cnt[ob + s] = cnt[s];
-        o_err[ob + s] = err[s];
+        o_item[s] = item[s];
+        o_cnt[s] = cnt[s];
+        o_err[s] = err[s];
     }
     if (lane == 0) {
-        o_size[c] = size;
-        o_min[c] = mo;
+        *o_size = size;
+        *o_min = mo;
+    }
+}
+
+// One wave per block c of C: [floor(c n / C), floor((c+1) n / C)) (Algorithm
+// 1's block bounds, 64-bit products, n < 2^32).  G: state slab gstate +
+// c * state_bytes.
+template <int P, bool G>
+__global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __restrict__ items, uint64_t n,
+                                                           uint32_t chunks, ChunkLayout L, int vec_ok,
+                                                           uint32_t* __restrict__ o_item,
+                                                           uint32_t* __restrict__ o_cnt,
+                                                           uint32_t* __restrict__ o_err,
+                                                           uint32_t* __restrict__ o_size,
+                                                           uint32_t* __restrict__ o_min,
+                                                           unsigned char* __restrict__ gstate) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t c = blockIdx.x;
+    unsigned char* sb = G ? gstate + (size_t)c * L.state_bytes : smem;
+    const uint64_t begin = (uint64_t)c * n / chunks;
+    const uint64_t end = (uint64_t)(c + 1) * n / chunks;
+    const uint64_t ob = (uint64_t)c * L.k;
+    summarize_block<P, G>(items, n, begin, end, L, vec_ok, sb, smem, o_item + ob, o_cnt + ob, o_err + ob, o_size + c,
+                          o_min + c);
+}
+
+// Batched form: every wave of a persistent grid takes blocks from a queue
+// (one counter per launch, zeroed before it) until the list is exhausted.
+// Blocks of one launch share P (their k fall in one size class); each block
+// carries its own stream, bounds, k and hash load factor.  W waves per
+// workgroup, each with its own LDS slab of lds_stride bytes.
+template <int P, int W>
+__global__ __launch_bounds__(64 * W) void batch_blocks_kernel(const BatchBlock* __restrict__ blocks,
+                                                              uint32_t nblocks, uint32_t* __restrict__ queue,
+                                                              uint32_t lds_stride, uint32_t* __restrict__ o_item,
+                                                              uint32_t* __restrict__ o_cnt,
+                                                              uint32_t* __restrict__ o_err,
+                                                              uint32_t* __restrict__ o_size,
+                                                              uint32_t* __restrict__ o_min) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char* lds = smem + (threadIdx.x / kWave) * lds_stride;
+    const uint32_t lane = lane_id();
+    for (;;) {
+        uint32_t b = 0;
+        if (lane == 0) b = atomicAdd(queue, 1u);
+        b = __builtin_amdgcn_readlane(b, 0);
+        if (b >= nblocks) break;
+        const BatchBlock bb = blocks[b];
+        const ChunkLayout L = ChunkLayout::make(bb.k, false, bb.slots_x16);
+        const int vec_ok = ((uintptr_t)bb.items & 15u) == 0;
+        summarize_block<P, false>(bb.items, bb.n, bb.begin, bb.end, L, vec_ok, lds, lds, o_item + bb.out,
+                                  o_cnt + bb.out, o_err + bb.out, o_size + b, o_min + b);
+        wave_sync();  // the slab is reused by the next block
+    }
+}
+
+template <int P, int W>
+static hipError_t launch_batch_pw(const BatchBlock* blocks, uint32_t nblocks, uint32_t* queue, uint32_t lds_stride,
+                                  uint32_t grid, const BlockSummaries& out, hipStream_t stream) {
+    const uint32_t lds = W * lds_stride;
+    hipFuncSetAttribute((const void*)batch_blocks_kernel<P, W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((batch_blocks_kernel<P, W>), dim3(grid), dim3(64 * W), lds, stream, blocks, nblocks, queue,
+                       lds_stride, out.item, out.cnt, out.err, out.size, out.min);
+    return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_batch_p(const BatchBlock* blocks, uint32_t nblocks, uint32_t* queue, uint32_t lds_stride,
+                                 uint32_t waves_per_group, uint32_t grid, const BlockSummaries& out,
+                                 hipStream_t stream) {
+    switch (waves_per_group) {
+    case 1: return launch_batch_pw<P, 1>(blocks, nblocks, queue, lds_stride, grid, out, stream);
+    case 2:
+        if constexpr (P <= 16) return launch_batch_pw<P, 2>(blocks, nblocks, queue, lds_stride, grid, out, stream);
+        return hipErrorInvalidValue;
+    case 4:
+        if constexpr (P <= 8) return launch_batch_pw<P, 4>(blocks, nblocks, queue, lds_stride, grid, out, stream);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_blocks(const BatchBlock* blocks, uint32_t nblocks, uint32_t* queue, uint32_t sort_lanes,
+                               uint32_t lds_stride, uint32_t waves_per_group, uint32_t grid,
+                               const BlockSummaries& out, hipStream_t stream) {
+    if (nblocks == 0) return hipSuccess;
+    switch (sort_lanes) {
+    case 1:
+    case 2: return launch_batch_p<2>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, stream);
+    case 4: return launch_batch_p<4>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, stream);
+    case 8: return launch_batch_p<8>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, stream);
+    case 16: return launch_batch_p<16>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, stream);
+    case 32: return launch_batch_p<32>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, stream);
+    case 64: return launch_batch_p<64>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, stream);
+    default: return hipErrorInvalidValue;
     }
 }
 

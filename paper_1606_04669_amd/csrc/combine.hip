@@ -276,6 +276,32 @@ __global__ __launch_bounds__(kCombineThreads) void merge_kernel(WideSummary d, W
                                                s.size[0], s.min[0], k, d.item, d.cnt, d.err, d.size, d.min, big, smem);
 }
 
+// One tree level of a batch: node j merges two block summaries of one
+// stream (any stream, any k up to the launch's bound) into the first.
+__global__ __launch_bounds__(kCombineThreads) void batch_combine_kernel(const BatchNode* __restrict__ nodes,
+                                                                        uint32_t count, BlockSummaries v) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t small = CombineLds<uint32_t>::make(2).small_bytes;  // independent of k
+    for (uint32_t j = blockIdx.x; j < count; j += gridDim.x) {
+        const BatchNode nd = nodes[j];
+        __syncthreads();  // the previous node is done with LDS
+        combine_node<uint32_t, uint32_t, uint32_t>(v.item + nd.a_off, v.cnt + nd.a_off, v.err + nd.a_off, v.size[nd.a],
+                                                   v.min[nd.a], v.item + nd.b_off, v.cnt + nd.b_off,
+                                                   v.err + nd.b_off, v.size[nd.b], v.min[nd.b], nd.k,
+                                                   v.item + nd.a_off, v.cnt + nd.a_off, v.err + nd.a_off,
+                                                   &v.size[nd.a], &v.min[nd.a], smem + small, smem);
+    }
+}
+
+hipError_t launch_batch_combine(const BatchNode* nodes, uint32_t count, uint32_t kmax, const BlockSummaries& base,
+                                hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    const uint32_t lds = combine_lds_bytes(kmax, false);
+    hipFuncSetAttribute((const void*)batch_combine_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(batch_combine_kernel, dim3(count), dim3(kCombineThreads), lds, stream, nodes, count, base);
+    return hipGetLastError();
+}
+
 uint32_t combine_lds_bytes(uint32_t k, bool wide) {
     return wide ? CombineLds<uint64_t>::make(k).big_bytes + CombineLds<uint64_t>::make(k).small_bytes
                 : CombineLds<uint32_t>::make(k).big_bytes + CombineLds<uint32_t>::make(k).small_bytes;

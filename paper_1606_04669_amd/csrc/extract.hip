@@ -30,20 +30,18 @@ __device__ __forceinline__ bool ext_better(uint64_t ca, uint64_t ea, uint32_t ia
     return ia < ib;
 }
 
-// G: the sort arrays live in a global scratch slab (k beyond LDS).
-template <bool G>
-__global__ __launch_bounds__(kExtractThreads) void extract_kernel(WideSummary s, uint32_t k, uint64_t N, int kind,
-                                                                  uint32_t cap, DevEntry* out, uint32_t* out_count,
-                                                                  unsigned char* scratch) {
-    extern __shared__ __align__(16) unsigned char smem[];
+// Canonical sort and report of one summary (entries s_item/s_cnt/s_err,
+// `size` of them) by one workgroup.  base: the sort arrays (LDS or a scratch
+// slab) for next_pow2(k) entries; small: 16 bytes of LDS.
+template <typename CT>
+__device__ void extract_body(const uint32_t* s_item, const CT* s_cnt, const CT* s_err, uint32_t size, uint32_t k,
+                             uint64_t N, int kind, uint32_t cap, DevEntry* out, uint32_t* out_count,
+                             unsigned char* base, uint32_t* small) {
     const uint32_t P0 = extract_cap(k);
-    unsigned char* base = G ? scratch : smem;
-    uint32_t* small = (uint32_t*)(G ? smem : smem + extract_big_bytes(k));
     uint64_t* cc = (uint64_t*)base;
     uint64_t* ce = cc + P0;
     uint32_t* ci = (uint32_t*)(ce + P0);
     const uint32_t tid = threadIdx.x;
-    const uint32_t size = s.size[0];
     if (size > k) {  // the summary carries the failure mark of a block kernel
         if (tid == 0) *out_count = 0xFFFFFFFFu;
         return;
@@ -52,9 +50,9 @@ __global__ __launch_bounds__(kExtractThreads) void extract_kernel(WideSummary s,
     if (P < 2) P = 2;
     for (uint32_t i = tid; i < P; i += kExtractThreads) {
         if (i < size) {
-            cc[i] = s.cnt[i];
-            ce[i] = s.err[i];
-            ci[i] = s.item[i];
+            cc[i] = s_cnt[i];
+            ce[i] = s_err[i];
+            ci[i] = s_item[i];
         } else {  // padding sorts after every real entry (real counts are >= 1)
             cc[i] = 0;
             ce[i] = ~0ull;
@@ -105,6 +103,54 @@ __global__ __launch_bounds__(kExtractThreads) void extract_kernel(WideSummary s,
         out[i] = e;
     }
     if (tid == 0) *out_count = q;
+}
+
+// G: the sort arrays live in a global scratch slab (k beyond LDS).
+template <bool G>
+__global__ __launch_bounds__(kExtractThreads) void extract_kernel(WideSummary s, uint32_t k, uint64_t N, int kind,
+                                                                  uint32_t cap, DevEntry* out, uint32_t* out_count,
+                                                                  unsigned char* scratch) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char* base = G ? scratch : smem;
+    uint32_t* small = (uint32_t*)(G ? smem : smem + extract_big_bytes(k));
+    extract_body<uint64_t>(s.item, s.cnt, s.err, s.size[0], k, N, kind, cap, out, out_count, base, small);
+}
+
+// Majority reports of a batch, one workgroup per stream, straight from the
+// root of its tree (32-bit counts).
+__global__ __launch_bounds__(kExtractThreads) void batch_extract_kernel(const BatchReport* __restrict__ reps,
+                                                                        uint32_t count, uint32_t kmax,
+                                                                        BlockSummaries v, DevEntry* out,
+                                                                        uint32_t* out_count) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* small = (uint32_t*)(smem + extract_big_bytes(kmax));
+    for (uint32_t j = blockIdx.x; j < count; j += gridDim.x) {
+        const BatchReport r = reps[j];
+        __syncthreads();  // the previous stream is done with LDS
+        extract_body<uint32_t>(v.item + r.root_off, v.cnt + r.root_off, v.err + r.root_off, v.size[r.root], r.k, r.n,
+                               0, r.k, out + r.out_off, out_count + j, smem, small);
+    }
+}
+
+hipError_t launch_batch_extract(const BatchReport* reps, uint32_t count, uint32_t kmax, const BlockSummaries& base,
+                                DevEntry* out, uint32_t* out_count, hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    const uint32_t lds = extract_lds_bytes(kmax);
+    hipFuncSetAttribute((const void*)batch_extract_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(batch_extract_kernel, dim3(count), dim3(kExtractThreads), lds, stream, reps, count, kmax, base,
+                       out, out_count);
+    return hipGetLastError();
+}
+
+__global__ void zero_words_kernel(uint32_t* p, uint32_t count) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+hipError_t launch_zero_words(uint32_t* p, uint32_t count, hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    const uint32_t grid = (count + 255) / 256 < 1024 ? (count + 255) / 256 : 1024;
+    hipLaunchKernelGGL(zero_words_kernel, dim3(grid), dim3(256), 0, stream, p, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_extract(const WideSummary& s, uint32_t k, uint64_t N, int kind, uint32_t cap, DevEntry* out,

@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include "pss.h"
+#include "pss_ctx.h"
 #include "pss_kernels.h"
 #include "pss_layout.h"
 
@@ -18,10 +19,6 @@ using namespace pss;
 
 namespace {
 
-constexpr uint32_t kMaxChunks = 1u << 22;
-// Largest k: the HBM-resident block state indexes counters and hash slots
-// with 32 bits, and the report sorts next_pow2(k) entries in one workgroup.
-constexpr uint32_t kMaxK = 1u << 20;
 // Device memory the HBM-resident block states of one update may take; the
 // planner lowers C below this.
 constexpr size_t kStateBudget = 16ull << 30;
@@ -29,53 +26,7 @@ constexpr size_t kStateBudget = 16ull << 30;
 // arrays do not fit LDS.
 constexpr uint32_t kCombineSlabsPerCu = 2;
 
-struct DeviceBuffer {
-    void* ptr = nullptr;
-    size_t bytes = 0;
-    int grow(size_t need) {
-        if (need <= bytes) return PSS_OK;
-        void* p = nullptr;
-        if (hipMalloc(&p, need) != hipSuccess) return PSS_ENOMEM;
-        if (ptr) hipFree(ptr);
-        ptr = p;
-        bytes = need;
-        return PSS_OK;
-    }
-    void release() {
-        if (ptr) hipFree(ptr);
-        ptr = nullptr;
-        bytes = 0;
-    }
-};
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
 }  // namespace
-
-struct PhaseMark {
-    int phase;
-    hipEvent_t a, b;
-};
-
-struct pss_ctx {
-    int device = 0;
-    bool timing = false;
-    std::vector<hipEvent_t> event_pool;
-    std::vector<PhaseMark> marks;
-    double phase_ms[4] = {0, 0, 0, 0};
-    uint32_t phase_n[4] = {0, 0, 0, 0};
-    int cu_count = 0;
-    size_t lds_max = 0;      // dynamic LDS per workgroup
-    size_t lds_per_cu = 0;
-    DeviceBuffer blocks;     // block summaries of one update
-    DeviceBuffer gstate;     // per-block state when it does not fit LDS
-    DeviceBuffer cscratch;   // COMBINE level slabs when they do not fit LDS
-    DeviceBuffer wscratch;   // fold / merge / report arrays when they do not fit LDS
-    DeviceBuffer query;      // report buffer
-    void* pinned = nullptr;  // host staging for reports
-    size_t pinned_bytes = 0;
-    std::map<uint32_t, pss_summary*> run_cache;
-};
 
 struct pss_summary {
     pss_ctx* ctx = nullptr;
@@ -86,18 +37,6 @@ struct pss_summary {
 };
 
 namespace {
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
-    }
-};
 
 BlockSummaries carve_blocks(void* base, uint32_t chunks, uint32_t k) {
     BlockSummaries v;
@@ -140,8 +79,6 @@ WideSummary carve_summary(void* base, uint32_t k) {
 }
 
 bool k_fits(const pss_ctx*, uint32_t k) { return k >= 2 && k <= kMaxK; }
-
-int check(hipError_t e) { return e == hipSuccess ? PSS_OK : PSS_EDEVICE; }
 
 // Where the arrays of each kernel live for k counters on this device.
 struct KPlan {

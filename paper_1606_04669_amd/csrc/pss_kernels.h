@@ -37,6 +37,50 @@ ChunkLayout chunk_layout(uint32_t k, size_t lds_max);
 hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L,
                                 const BlockSummaries& out, unsigned char* gstate, hipStream_t stream);
 
+// ---- batched form: many independent streams in one launch sequence ----
+
+// One block of a batch: items[begin, end) of a stream of n items, k counters.
+struct BatchBlock {
+    const uint32_t* items;  // the stream (device memory)
+    uint64_t n;             // stream length: bounds every load
+    uint64_t begin, end;    // block bounds within the stream (Algorithm 1)
+    uint64_t out;           // entry offset of the block summary (capacity k)
+    uint32_t k;
+    uint32_t slots_x16;     // hash slots per counter (x16), result-neutral
+};
+
+// One COMBINE of a batch level: summaries a and b (entry offsets a_off,
+// b_off, header indices a, b) into a, with k counters.
+struct BatchNode {
+    uint64_t a_off, b_off;
+    uint32_t a, b, k, pad;
+};
+
+// The report of one stream of a batch: the root summary (entry offset,
+// header index), k, the stream length n, and where its entries go.
+struct BatchReport {
+    uint64_t root_off;
+    uint64_t n;
+    uint64_t out_off;
+    uint32_t root, k;
+};
+
+// Persistent launch over nblocks blocks whose k share sort_lanes_per_k;
+// queue: one zeroed counter; waves_per_group waves per workgroup, each with
+// lds_stride bytes of LDS (>= the layout of every block's k and load factor).
+hipError_t launch_batch_blocks(const BatchBlock* blocks, uint32_t nblocks, uint32_t* queue, uint32_t sort_lanes,
+                               uint32_t lds_stride, uint32_t waves_per_group, uint32_t grid,
+                               const BlockSummaries& out, hipStream_t stream);
+// One tree level of a batch (all streams): nodes[0, count), kmax bounds LDS.
+hipError_t launch_batch_combine(const BatchNode* nodes, uint32_t count, uint32_t kmax, const BlockSummaries& base,
+                                hipStream_t stream);
+// Majority reports of a batch: one workgroup per stream; out_count[s] is the
+// number of entries written at out + out_off.
+hipError_t launch_batch_extract(const BatchReport* reps, uint32_t count, uint32_t kmax, const BlockSummaries& base,
+                                DevEntry* out, uint32_t* out_count, hipStream_t stream);
+// Zero `count` words (a kernel, safe inside captured graphs).
+hipError_t launch_zero_words(uint32_t* p, uint32_t count, hipStream_t stream);
+
 // One level of the fixed tree over `count` block summaries: node j combines
 // summaries 2*step*j and 2*step*j + step into position 2*step*j.
 // in_lds: the O(k) arrays of a COMBINE fit LDS (combine_lds_bytes <= limit);

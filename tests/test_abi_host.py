@@ -28,7 +28,8 @@ def lib():
 def test_header_declares_the_boundary():
     fns = declared_functions()
     for f in ["pss_ctx_create", "pss_ctx_destroy", "pss_create", "pss_destroy", "pss_update", "pss_merge",
-              "pss_query", "pss_run", "pss_strerror", "pss_block_summaries", "pss_plan_chunks", "pss_max_k"]:
+              "pss_query", "pss_run", "pss_strerror", "pss_block_summaries", "pss_plan_chunks", "pss_max_k",
+              "pss_batch_create", "pss_batch_run", "pss_batch_destroy", "pss_run_batched"]:
         assert f in fns
 
 
@@ -58,12 +59,20 @@ def test_strerror_and_null_handling_without_gpu(lib):
     lib.pss_destroy(None)
     lib.pss_ctx_destroy.argtypes = [ctypes.c_void_p]
     lib.pss_ctx_destroy(None)
+    lib.pss_batch_create.argtypes = [ctypes.c_void_p, ctypes.c_uint32] + [ctypes.c_void_p] * 4 + [ctypes.c_int,
+                                                                                                  ctypes.c_void_p]
+    assert lib.pss_batch_create(None, 1, None, None, None, None, 0, None) == -1
+    lib.pss_batch_run.argtypes = [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 3
+    assert lib.pss_batch_run(None, 0, None, None, None) == -1
+    lib.pss_batch_destroy.argtypes = [ctypes.c_void_p]
+    lib.pss_batch_destroy(None)
 
 
 def test_binding_names_match_the_abi():
     from paper_1606_04669_amd import binding
     for f in ["pss_ctx_create", "pss_ctx_destroy", "pss_create", "pss_destroy", "pss_update", "pss_merge",
-              "pss_query", "pss_run", "pss_block_summaries", "strerror"]:
+              "pss_query", "pss_run", "pss_block_summaries", "strerror", "pss_batch_create", "pss_batch_run",
+              "pss_batch_destroy", "pss_run_batched"]:
         assert callable(getattr(binding, f))
     assert binding.ENTRY_DTYPE.itemsize == 24
 

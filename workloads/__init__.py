@@ -184,3 +184,23 @@ def plain_highk(seed: int = 1, n: int = 1 << 31) -> Stream:
 
 def plain_highk_adversarial(seed: int = 1, n: int = 1 << 31) -> Stream:
     return Stream("plain_highk_adversarial", "adversarial", n, 0.0, 1 << 32, seed)
+
+
+def batched(seed: int = 1, nstreams: int = 4096, log10_min: float = 3.0, log10_max: float = 7.0,
+            k_min: int = 50, k_max: int = 2000):
+    """Batched case: nstreams independent streams.  Stream s has length
+    floor(10^(log10_min + (log10_max - log10_min) u)), Zipf alpha uniform in
+    [0.8, 2.0] over 2^32 hashed ids with its own key, and k uniform in
+    {k_min..k_max} (capped at its length).  Returns a list of (Stream, k)."""
+    key = subkey(seed, 10)
+    out = []
+    for s in range(nstreams):
+        u1 = (draw(key, 3 * s) >> 11) * 2.0 ** -53
+        u2 = (draw(key, 3 * s + 1) >> 11) * 2.0 ** -53
+        r3 = draw(key, 3 * s + 2)
+        n = int(10.0 ** (log10_min + (log10_max - log10_min) * u1))
+        alpha = 0.8 + 1.2 * u2
+        k = min(k_min + r3 % (k_max - k_min + 1), n)
+        sub = draw(key ^ 0xBA7C4ED, s)  # the stream's own seed
+        out.append((Stream("batched_%d" % s, "zipf_hashed", n, alpha, 1 << 32, sub), k))
+    return out

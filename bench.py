@@ -108,6 +108,82 @@ def cpu_baseline(streams, ks, host, chunks_of, sample_log2: int):
     }
 
 
+def percentile(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(round(q / 100.0 * (len(xs) - 1))))]
+
+
+def batched_leg(B, ctx, seed: int, replays: int, nstreams: int):
+    """Batched streams in one graph launch vs the same streams through
+    per-stream plain calls (same k and C, so the same results)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    cases = W.batched(seed, nstreams)
+    t = time.perf_counter()
+    dev, host_n = [], 0
+    for st, _ in cases:
+        a = st.generate()
+        host_n += len(a)
+        dev.append(torch.from_numpy(a.view(np.int32)).to("cuda"))
+    ks = [k for _, k in cases]
+    torch.cuda.synchronize()
+    log("batched: generated %d streams, %d items in %.1fs" % (len(cases), host_n, time.perf_counter() - t))
+    stream = torch.cuda.current_stream()
+    t = time.perf_counter()
+    b = B.Batch(ctx, dev, ks, None)
+    create_s = time.perf_counter() - t
+    info = b.info()
+    log("batched: plan + autotune + capture in %.2fs: %s" % (create_s, info))
+    res = b.run(stream=stream)  # warm-up replay
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        tr = time.perf_counter()
+        res = b.run(stream=stream)
+        lat.append((time.perf_counter() - tr) * 1e3)
+    batched_s = time.perf_counter() - t0
+    log("batched: %d replays done" % replays)
+    # the same streams through the plain path, one call each
+    # an untimed pass first (it also allocates the plain path's per-k
+    # summaries and workspaces) and checks every stream against the batch
+    same = True
+    for s in range(len(dev)):
+        got, _ = B.pss_run(ctx, dev[s], k=ks[s], chunks=b.chunks[s], stream=stream)
+        if same and B.to_tuples(got) != B.to_tuples(res[s]):
+            same = False
+    plain_lat = []
+    t0 = time.perf_counter()
+    for s in range(len(dev)):
+        tr = time.perf_counter()
+        B.pss_run(ctx, dev[s], k=ks[s], chunks=b.chunks[s], stream=stream)
+        plain_lat.append((time.perf_counter() - tr) * 1e3)
+    plain_s = time.perf_counter() - t0
+    log("batched: per-stream plain pass done")
+    b.close()
+    del dev
+    torch.cuda.empty_cache()
+    batched_v = host_n * replays / batched_s / 1e9
+    plain_v = host_n / plain_s / 1e9
+    return {
+        "workload": "batched: %d streams, lengths log-uniform in [10^3, 10^7] (total %d items), Zipf alpha "
+                    "U[0.8, 2.0] over 2^32 hashed ids, k uniform in {50..2000}; C per stream from the autotuner"
+                    % (len(cases), host_n),
+        "items": host_n,
+        "g_items_per_s": round(batched_v, 3),
+        "ms_per_replay_p50": round(percentile(lat, 50), 3),
+        "ms_per_replay_p99": round(percentile(lat, 99), 3),
+        "replays": replays,
+        "plain_per_stream_g_items_per_s": round(plain_v, 3),
+        "plain_per_call_ms_p50": round(percentile(plain_lat, 50), 3),
+        "plain_per_call_ms_p99": round(percentile(plain_lat, 99), 3),
+        "speedup_vs_plain": round(batched_v / plain_v, 3),
+        "identical_to_plain": same,
+        "plan_autotune_capture_s": round(create_s, 3),
+        "tuning": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in info.items()},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +194,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=24)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--batched-streams", type=int, default=4096)
+    ap.add_argument("--batched-replays", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise kernel of known traffic (for counter runs)")
     args = ap.parse_args()
@@ -227,6 +306,10 @@ def main():
             "reduction_share": round((ms[1] + ms[2]) / total_ms, 4) if total_ms else None,
         },
     }
+    if not args.no_batched:
+        del dev
+        torch.cuda.empty_cache()
+        result["batched"] = batched_leg(B, ctx, args.seed, args.batched_replays, args.batched_streams)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         result["cpu_baseline"] = cpu_baseline(streams, ks, host, chunks_of, args.cpu_sample_log2)

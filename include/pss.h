@@ -192,6 +192,74 @@ void pss_batch_destroy(pss_batch* b);
 int pss_run_batched(pss_ctx* ctx, uint32_t nstreams, const uint32_t* const* h_items, const uint64_t* h_lens,
                     const uint32_t* h_ks, uint32_t* h_chunks, pss_entry* h_out, uint32_t* h_counts, void* stream);
 
+/* ---- Served form: a pool of device-resident summaries and a request loop ----
+ *
+ * Summary sid (k = h_ks[sid] counters, starting empty) lives in device
+ * memory for the life of the server.  An append of n items is exactly
+ * pss_update on that summary (B = fixed-tree COMBINE of the Space Saving
+ * summaries of the C blocks of the items, then S <- COMBINE(S, B),
+ * N <- N + n); a query is pss_query.  Requests on one summary take effect in
+ * submission order.  A server thread batches pending requests into launches
+ * (continuous batching: requests that arrive while launches run are admitted
+ * into the next launch as slots and memory free up), several launches in
+ * flight at once; device memory for staged items and launch workspace is
+ * bounded by opts.hbm_budget. */
+typedef struct pss_server pss_server;
+
+typedef struct {
+    uint64_t hbm_budget;   /* device bytes for staged items + launch workspace (0: 64 GiB), split over slots */
+    uint32_t slots;        /* launches in flight (0: 2; at most 8) */
+    uint32_t max_requests; /* requests per launch (0: 4096) */
+    uint64_t block_len;    /* target block length for appends with chunks = 0 (0: 16384) */
+} pss_server_opts;
+
+typedef struct {
+    int status;            /* PSS_OK or the error the request ended with */
+    uint32_t n_out;        /* entries reported (majority: before truncation to cap) */
+    uint64_t stream_len;   /* N of the summary after this append / at this query */
+    uint32_t chunks_used;  /* C of an append (record it to reproduce results) */
+    uint32_t launch;       /* the launch that ran the request (0: none needed) */
+    double latency_ms;     /* submission to completion */
+    double queue_ms;       /* submission to admission into a launch */
+} pss_server_result;
+
+typedef struct {
+    uint64_t launches, requests, items_appended;
+    uint32_t max_launch_requests, pending;
+    int status;            /* PSS_OK, or the error that stopped the server */
+} pss_server_stats_t;
+
+/* Largest k a served summary may have on this context. */
+uint32_t pss_server_max_k(const pss_ctx* ctx);
+
+/* Start a server with nsummaries empty summaries (k = h_ks[i]; 2 <= k <=
+ * pss_server_max_k(), else PSS_EINVAL / PSS_ERANGE).  opts may be NULL. */
+int pss_server_create(pss_ctx* ctx, uint32_t nsummaries, const uint32_t* h_ks, const pss_server_opts* opts,
+                      pss_server** out);
+
+/* Finish every submitted request, stop the thread, release the pool. */
+void pss_server_destroy(pss_server* srv);
+
+/* Submit an append of h_items[0, n) (host memory, caller-owned, valid until
+ * the ticket completes) to summary sid with C = chunks blocks (0: chosen from
+ * opts.block_len, reported by pss_server_wait).  Returns at once with
+ * *ticket.  PSS_ERANGE if n >= 2^32 or the append can never fit the budget. */
+int pss_server_append(pss_server* srv, uint32_t sid, const uint32_t* h_items, uint64_t n, uint32_t chunks,
+                      uint64_t* ticket);
+
+/* Submit a query of summary sid (kind as pss_query; cap bounds a top query).
+ * Returns at once with *ticket. */
+int pss_server_query(pss_server* srv, uint32_t sid, int kind, uint32_t cap, uint64_t* ticket);
+
+/* Wait for a ticket (each ticket once): fills *res and, for a query, up to
+ * cap entries of h_out (canonical order).  Returns the request's status, or
+ * PSS_ETRUNC for a majority query with more than cap entries, or PSS_EINVAL
+ * for an unknown ticket. */
+int pss_server_wait(pss_server* srv, uint64_t ticket, pss_entry* h_out, uint32_t cap, pss_server_result* res);
+
+/* Counters of the server since it started. */
+int pss_server_stats(pss_server* srv, pss_server_stats_t* st);
+
 /* Phase timing.  While enabled, pss_update, pss_run and pss_query record HIP
  * events on the call's stream around each phase: 0 = block summaries
  * (chunk_summary kernel), 1 = COMBINE tree, 2 = fold into the summary,

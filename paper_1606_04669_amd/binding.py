@@ -34,6 +34,31 @@ class BatchInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ServerOpts(ctypes.Structure):
+    """pss_server_opts"""
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_uint32), ("max_requests", ctypes.c_uint32),
+                ("block_len", ctypes.c_uint64)]
+
+
+class ServerResult(ctypes.Structure):
+    """pss_server_result"""
+    _fields_ = [("status", ctypes.c_int), ("n_out", ctypes.c_uint32), ("stream_len", ctypes.c_uint64),
+                ("chunks_used", ctypes.c_uint32), ("launch", ctypes.c_uint32), ("latency_ms", ctypes.c_double),
+                ("queue_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    """pss_server_stats_t"""
+    _fields_ = [("launches", ctypes.c_uint64), ("requests", ctypes.c_uint64), ("items_appended", ctypes.c_uint64),
+                ("max_launch_requests", ctypes.c_uint32), ("pending", ctypes.c_uint32), ("status", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class PssError(RuntimeError):
     def __init__(self, code: int, what: str, required: int | None = None):
         self.code = code
@@ -79,11 +104,21 @@ def lib():
         L.pss_batch_destroy.argtypes = [vp]
         L.pss_batch_destroy.restype = None
         L.pss_run_batched.argtypes = [vp, u32, vp, u64p, u32p, u32p, vp, u32p, vp]
+        L.pss_server_max_k.restype = u32
+        L.pss_server_max_k.argtypes = [vp]
+        L.pss_server_create.argtypes = [vp, u32, u32p, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+        L.pss_server_destroy.argtypes = [vp]
+        L.pss_server_destroy.restype = None
+        L.pss_server_append.argtypes = [vp, u32, vp, u64, u32, u64p]
+        L.pss_server_query.argtypes = [vp, u32, i32, u32, u64p]
+        L.pss_server_wait.argtypes = [vp, u64, vp, u32, ctypes.POINTER(ServerResult)]
+        L.pss_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
         L.pss_timing_enable.argtypes = [vp, i32]
         L.pss_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), u32p, i32]
         for f in ("pss_timing_enable", "pss_phase_times", "pss_ctx_create", "pss_create", "pss_update", "pss_merge",
                   "pss_query", "pss_run", "pss_block_summaries", "pss_batch_create", "pss_batch_run", "pss_batch_info",
-                  "pss_run_batched"):
+                  "pss_run_batched", "pss_server_create", "pss_server_append", "pss_server_query", "pss_server_wait",
+                  "pss_server_stats"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -141,6 +176,10 @@ class Context:
     @property
     def max_lds_k(self) -> int:
         return int(lib().pss_max_lds_k(self.handle))
+
+    @property
+    def server_max_k(self) -> int:
+        return int(lib().pss_server_max_k(self.handle))
 
     @property
     def batch_max_k(self) -> int:
@@ -346,6 +385,65 @@ def pss_run_batched(ctx: Context, streams, ks, chunks=None, stream=None):
                                  counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                  ctypes.c_void_p(_stream(stream))), "pss_run_batched")
     return _split_reports(out, counts, [int(k) for k in a_k]), [int(c) for c in a_c]
+
+
+class Server:
+    """pss_server: a pool of device-resident summaries (one per k in ks) served
+    by the library's request loop.  Appends take host uint32 arrays, kept
+    referenced here until their ticket is waited for."""
+
+    def __init__(self, ctx: Context, ks, hbm_budget: int = 0, slots: int = 0, max_requests: int = 0,
+                 block_len: int = 0):
+        a_k = np.ascontiguousarray(np.asarray(ks, dtype=np.uint32))
+        opts = ServerOpts(hbm_budget, slots, max_requests, block_len)
+        h = ctypes.c_void_p()
+        _check(lib().pss_server_create(ctx.handle, len(a_k), a_k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                       ctypes.byref(opts), ctypes.byref(h)), "pss_server_create")
+        self.handle = h
+        self.ctx = ctx
+        self.ks = [int(k) for k in a_k]
+        self._hold = {}
+
+    def append(self, sid: int, items, chunks: int = 0) -> int:
+        a = np.ascontiguousarray(np.asarray(items, dtype=np.uint32))
+        t = ctypes.c_uint64()
+        _check(lib().pss_server_append(self.handle, sid, a.ctypes.data_as(ctypes.c_void_p), len(a), chunks,
+                                       ctypes.byref(t)), "pss_server_append")
+        self._hold[int(t.value)] = a
+        return int(t.value)
+
+    def query(self, sid: int, kind: int = PSS_Q_MAJORITY, cap: int | None = None) -> int:
+        t = ctypes.c_uint64()
+        cap = self.ks[sid] if cap is None else cap
+        _check(lib().pss_server_query(self.handle, sid, kind, cap, ctypes.byref(t)), "pss_server_query")
+        return int(t.value)
+
+    def wait(self, ticket: int, cap: int | None = None):
+        """(entries, result dict); entries is empty for an append."""
+        cap = max(self.ks) if cap is None else cap
+        out = np.zeros(max(cap, 1), dtype=ENTRY_DTYPE)
+        res = ServerResult()
+        rc = lib().pss_server_wait(self.handle, ticket, out.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(res))
+        self._hold.pop(ticket, None)
+        _check(rc, "pss_server_wait", int(res.n_out))
+        return out[: min(int(res.n_out), cap)].copy(), res.as_dict()
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().pss_server_stats(self.handle, ctypes.byref(st)), "pss_server_stats")
+        return st.as_dict()
+
+    def close(self):
+        if self.handle:
+            lib().pss_server_destroy(self.handle)
+            self.handle = None
+            self._hold.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def to_tuples(entries):

@@ -302,6 +302,33 @@ hipError_t launch_batch_combine(const BatchNode* nodes, uint32_t count, uint32_t
     return hipGetLastError();
 }
 
+// Served appends: S_sid <- COMBINE(S_sid, root of the append's tree) for
+// every append of a launch (one per summary), u64 counts in the summaries.
+__global__ __launch_bounds__(kCombineThreads) void serve_fold_kernel(const ServeFold* __restrict__ f, uint32_t count,
+                                                                     WideSummary pool, BlockSummaries v) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t small = CombineLds<uint64_t>::make(2).small_bytes;  // independent of k
+    for (uint32_t j = blockIdx.x; j < count; j += gridDim.x) {
+        const ServeFold d = f[j];
+        __syncthreads();  // the previous fold is done with LDS
+        combine_node<uint64_t, uint32_t, uint64_t>(pool.item + d.s_off, pool.cnt + d.s_off, pool.err + d.s_off,
+                                                   pool.size[d.sid], pool.min[d.sid], v.item + d.root_off,
+                                                   v.cnt + d.root_off, v.err + d.root_off, v.size[d.root],
+                                                   v.min[d.root], d.k, pool.item + d.s_off, pool.cnt + d.s_off,
+                                                   pool.err + d.s_off, &pool.size[d.sid], &pool.min[d.sid],
+                                                   smem + small, smem);
+    }
+}
+
+hipError_t launch_serve_fold(const ServeFold* f, uint32_t count, uint32_t kmax, const WideSummary& pool,
+                             const BlockSummaries& blocks, hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    const uint32_t lds = combine_lds_bytes(kmax, true);
+    hipFuncSetAttribute((const void*)serve_fold_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(serve_fold_kernel, dim3(count), dim3(kCombineThreads), lds, stream, f, count, pool, blocks);
+    return hipGetLastError();
+}
+
 uint32_t combine_lds_bytes(uint32_t k, bool wide) {
     return wide ? CombineLds<uint64_t>::make(k).big_bytes + CombineLds<uint64_t>::make(k).small_bytes
                 : CombineLds<uint32_t>::make(k).big_bytes + CombineLds<uint32_t>::make(k).small_bytes;

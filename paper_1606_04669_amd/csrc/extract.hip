@@ -142,6 +142,32 @@ hipError_t launch_batch_extract(const BatchReport* reps, uint32_t count, uint32_
     return hipGetLastError();
 }
 
+// Served queries: one workgroup per query on a persistent summary of the
+// pool (u64 counts), kind and cap per query.
+__global__ __launch_bounds__(kExtractThreads) void serve_query_kernel(const ServeQuery* __restrict__ q,
+                                                                      uint32_t count, uint32_t kmax,
+                                                                      WideSummary pool, DevEntry* out,
+                                                                      uint32_t* out_count) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* small = (uint32_t*)(smem + extract_big_bytes(kmax));
+    for (uint32_t j = blockIdx.x; j < count; j += gridDim.x) {
+        const ServeQuery d = q[j];
+        __syncthreads();  // the previous query is done with LDS
+        extract_body<uint64_t>(pool.item + d.s_off, pool.cnt + d.s_off, pool.err + d.s_off, pool.size[d.sid], d.k,
+                               d.n, (int)d.kind, d.cap, out + d.out_off, out_count + j, smem, small);
+    }
+}
+
+hipError_t launch_serve_query(const ServeQuery* q, uint32_t count, uint32_t kmax, const WideSummary& pool,
+                              DevEntry* out, uint32_t* out_count, hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    const uint32_t lds = extract_lds_bytes(kmax);
+    hipFuncSetAttribute((const void*)serve_query_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(serve_query_kernel, dim3(count), dim3(kExtractThreads), lds, stream, q, count, kmax, pool, out,
+                       out_count);
+    return hipGetLastError();
+}
+
 __global__ void zero_words_kernel(uint32_t* p, uint32_t count) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
 }

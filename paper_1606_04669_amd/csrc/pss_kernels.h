@@ -78,6 +78,28 @@ hipError_t launch_batch_combine(const BatchNode* nodes, uint32_t count, uint32_t
 // number of entries written at out + out_off.
 hipError_t launch_batch_extract(const BatchReport* reps, uint32_t count, uint32_t kmax, const BlockSummaries& base,
                                 DevEntry* out, uint32_t* out_count, hipStream_t stream);
+// ---- served form: appends and queries on a pool of persistent summaries ----
+// Pool: summary sid's entries at offset s_off of item/cnt/err, header at
+// size[sid], min[sid].
+
+// S_sid <- COMBINE(S_sid, block summary `root`) with k counters.
+struct ServeFold {
+    uint64_t s_off, root_off;
+    uint32_t sid, root, k, pad;
+};
+
+// Report of summary sid (kind 0: count * k > n; 1: first cap), entries to
+// out + out_off.
+struct ServeQuery {
+    uint64_t s_off, n, out_off;
+    uint32_t sid, k, kind, cap;
+};
+
+hipError_t launch_serve_fold(const ServeFold* f, uint32_t count, uint32_t kmax, const WideSummary& pool,
+                             const BlockSummaries& blocks, hipStream_t stream);
+hipError_t launch_serve_query(const ServeQuery* q, uint32_t count, uint32_t kmax, const WideSummary& pool,
+                              DevEntry* out, uint32_t* out_count, hipStream_t stream);
+
 // Zero `count` words (a kernel, safe inside captured graphs).
 hipError_t launch_zero_words(uint32_t* p, uint32_t count, hipStream_t stream);
 

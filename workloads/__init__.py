@@ -204,3 +204,40 @@ def batched(seed: int = 1, nstreams: int = 4096, log10_min: float = 3.0, log10_m
         sub = draw(key ^ 0xBA7C4ED, s)  # the stream's own seed
         out.append((Stream("batched_%d" % s, "zipf_hashed", n, alpha, 1 << 32, sub), k))
     return out
+
+
+def served_append(n: int, alpha: float, summary_key: int, request_seed: int,
+                  out: np.ndarray | None = None) -> np.ndarray:
+    """Items of one served append: Zipf(alpha) ranks over 2^32 drawn from the
+    request's own seed, mapped to ids with the target summary's key, so that
+    every append to one summary draws from the same id distribution."""
+    out = np.empty(n, dtype=np.uint32) if out is None else out
+    rc = _load().wl_zipf_hashed(_u32ptr(out), n, alpha, 1 << 32, subkey(request_seed, 1),
+                                summary_key & 0xFFFFFFFF, 1)
+    if rc != 0:
+        raise RuntimeError("wl_zipf_hashed failed: %d" % rc)
+    return out
+
+
+def served_log(seed: int = 1, nsummaries: int = 10000, nrequests: int = 20000, max_log2: float = 20.0,
+               alpha: float = 1.3, append_share: float = 0.9, k_min: int = 100, k_max: int = 1000):
+    """Served case: summary ks (uniform in {k_min..k_max}) and a request log.
+    Each request targets a uniform summary; with probability append_share it
+    is an append of floor(2^(max_log2 u)) items (log-uniform in [1, 2^max_log2])
+    of Zipf(alpha) ids with that summary's key, else a query, top or majority
+    with equal odds.  Returns (ks, keys, requests) with requests a list of
+    ("append", sid, n, request_seed) or ("query", sid, kind)."""
+    key = subkey(seed, 20)
+    ks = [k_min + draw(key, s) % (k_max - k_min + 1) for s in range(nsummaries)]
+    keys = [draw(key ^ 0x5E4, s) for s in range(nsummaries)]
+    reqs = []
+    rk = subkey(seed, 21)
+    for i in range(nrequests):
+        r0, r1, r2 = draw(rk, 3 * i), draw(rk, 3 * i + 1), draw(rk, 3 * i + 2)
+        sid = r0 % nsummaries
+        if (r1 >> 11) * 2.0 ** -53 < append_share:
+            n = int(2.0 ** (max_log2 * ((r2 >> 11) * 2.0 ** -53)))
+            reqs.append(("append", sid, n, draw(rk ^ 0xA99, i)))
+        else:
+            reqs.append(("query", sid, int(r2 & 1)))
+    return ks, keys, reqs

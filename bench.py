@@ -184,6 +184,96 @@ def batched_leg(B, ctx, seed: int, replays: int, nstreams: int):
     }
 
 
+def served_leg(B, ctx, seed: int, nrequests: int, loads):
+    """Open-loop Poisson arrivals of appends and queries (90:10) on 10^4
+    device-resident summaries, at each offered load (requests/s; 0 = all at
+    once, saturation), through the library's request loop; then the same log
+    through one plain call per request (pss_update / pss_query)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    nsum = 10000
+    ks, keys, reqs = W.served_log(seed, nsum, nrequests)
+    t = time.perf_counter()
+    data = [W.served_append(r[2], 1.3, keys[r[1]], r[3]) if r[0] == "append" else None for r in reqs]
+    items = sum(len(d) for d in data if d is not None)
+    log("served: %d requests, %d appended items, generated in %.1fs" % (len(reqs), items, time.perf_counter() - t))
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0, len(reqs))
+    levels = []
+    for lam in loads:
+        srv = B.Server(ctx, ks)
+        arrivals = np.cumsum(gaps) / lam if lam > 0 else np.zeros(len(reqs))
+        tickets, sub = [], []
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            if lam > 0:
+                while time.perf_counter() - t0 < arrivals[i]:
+                    pass
+            sub.append(time.perf_counter() - t0)
+            if r[0] == "append":
+                tickets.append(srv.append(r[1], data[i]))
+            else:
+                tickets.append(srv.query(r[1], B.PSS_Q_MAJORITY if r[2] == 0 else B.PSS_Q_TOPK, cap=ks[r[1]]))
+        submit_s = time.perf_counter() - t0
+        lat = []
+        for tk in tickets:
+            _, res = srv.wait(tk)
+            lat.append(res["latency_ms"])
+        # last completion as the server saw it (submission + latency), not
+        # when this loop got round to collecting it
+        wall = max(sb + l / 1e3 for sb, l in zip(sub, lat))
+        st = srv.stats()
+        srv.close()
+        levels.append({
+            "offered_req_per_s": lam if lam > 0 else "all at t=0",
+            "achieved_req_per_s": round(len(reqs) / wall, 1),
+            "g_items_per_s": round(items / wall / 1e9, 3),
+            "latency_ms_p50": round(percentile(lat, 50), 3),
+            "latency_ms_p99": round(percentile(lat, 99), 3),
+            "launches": st["launches"],
+            "max_requests_per_launch": st["max_launch_requests"],
+            "submit_s": round(submit_s, 3),
+            "host_staging_ms": round(st["stage_ms"], 1),
+            "device_ms": round(st["gpu_ms"], 1),
+        })
+        log("served: load %s done: %s" % (lam, levels[-1]))
+    # the same log through plain calls, one request at a time, items copied
+    # from host memory per request as the server does
+    summaries = {}
+    stream = torch.cuda.current_stream()
+    for sid in sorted(set(r[1] for r in reqs)):
+        summaries[sid] = B.Summary(ctx, ks[sid])
+    plain_lat = []
+    t0 = time.perf_counter()
+    for i, r in enumerate(reqs):
+        tr = time.perf_counter()
+        s = summaries[r[1]]
+        if r[0] == "append":
+            d = torch.from_numpy(data[i].view(np.int32)).to("cuda", non_blocking=False)
+            B.pss_update(s, d, stream=stream)
+            stream.synchronize()
+        else:
+            B.pss_query(s, B.PSS_Q_MAJORITY if r[2] == 0 else B.PSS_Q_TOPK, cap=ks[r[1]], stream=stream)
+        plain_lat.append((time.perf_counter() - tr) * 1e3)
+    plain_wall = time.perf_counter() - t0
+    for s in summaries.values():
+        s.close()
+    best = max(levels, key=lambda x: x["g_items_per_s"])
+    return {
+        "workload": "served: %d device-resident summaries (k uniform in {100..1000}); %d requests, 90%% appends of "
+                    "log-uniform length in [1, 2^20] (Zipf 1.3 over 2^32, per-summary ids), 10%% top/majority "
+                    "queries; open-loop Poisson arrivals" % (nsum, len(reqs)),
+        "items": items,
+        "levels": levels,
+        "saturation_g_items_per_s": best["g_items_per_s"],
+        "plain_per_request_g_items_per_s": round(items / plain_wall / 1e9, 3),
+        "plain_per_request_ms_p50": round(percentile(plain_lat, 50), 3),
+        "plain_per_request_ms_p99": round(percentile(plain_lat, 99), 3),
+        "speedup_vs_plain": round(best["g_items_per_s"] / (items / plain_wall / 1e9), 3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +285,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=24)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--no-served", action="store_true", help="skip the served leg")
+    ap.add_argument("--served-requests", type=int, default=4000)
+    ap.add_argument("--served-loads", default="2000,10000,40000,0",
+                    help="offered loads in requests/s (0: all at once)")
     ap.add_argument("--batched-streams", type=int, default=4096)
     ap.add_argument("--batched-replays", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -310,6 +404,9 @@ def main():
         del dev
         torch.cuda.empty_cache()
         result["batched"] = batched_leg(B, ctx, args.seed, args.batched_replays, args.batched_streams)
+    if not args.no_served:
+        result["served"] = served_leg(B, ctx, args.seed, args.served_requests,
+                                      [float(x) for x in args.served_loads.split(",")])
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         result["cpu_baseline"] = cpu_baseline(streams, ks, host, chunks_of, args.cpu_sample_log2)

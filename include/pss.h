@@ -227,6 +227,8 @@ typedef struct {
     uint64_t launches, requests, items_appended;
     uint32_t max_launch_requests, pending;
     int status;            /* PSS_OK, or the error that stopped the server */
+    double stage_ms;       /* host time copying append items into pinned staging */
+    double gpu_ms;         /* device time of the launches (copies included; launches overlap) */
 } pss_server_stats_t;
 
 /* Largest k a served summary may have on this context. */

@@ -53,7 +53,8 @@ class ServerResult(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     """pss_server_stats_t"""
     _fields_ = [("launches", ctypes.c_uint64), ("requests", ctypes.c_uint64), ("items_appended", ctypes.c_uint64),
-                ("max_launch_requests", ctypes.c_uint32), ("pending", ctypes.c_uint32), ("status", ctypes.c_int)]
+                ("max_launch_requests", ctypes.c_uint32), ("pending", ctypes.c_uint32), ("status", ctypes.c_int),
+                ("stage_ms", ctypes.c_double), ("gpu_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -78,6 +78,7 @@ struct Request {
 struct Slot {
     hipStream_t st = nullptr;
     hipEvent_t done = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;  // device time of the launch
     bool busy = false;
     uint64_t seq = 0;  // launch number running on the slot
     std::vector<Request*> reqs;
@@ -147,6 +148,7 @@ struct pss_server {
     // statistics
     uint64_t launches = 0, requests = 0, appended = 0;
     uint32_t max_launch_requests = 0;
+    double stage_ms = 0.0, gpu_ms = 0.0;
 };
 
 namespace {
@@ -156,6 +158,44 @@ namespace {
 size_t append_bytes(uint64_t n, uint32_t k, uint32_t C) {
     return align_up(n * 4, 16) + (size_t)C * k * 12 + (size_t)C * 8 + (size_t)C * sizeof(BatchBlock) +
            (size_t)C * sizeof(BatchNode) + sizeof(ServeFold);
+}
+
+// Copies every append's items into the pinned staging buffer; large launches
+// split the bytes over several threads (one core does not reach the host's
+// memory bandwidth).
+void stage_items(const Slot& sl, char* hp, const std::vector<uint64_t>& item_off, uint64_t total_bytes) {
+    struct Piece {
+        char* dst;
+        const char* src;
+        size_t bytes;
+    };
+    std::vector<Piece> pieces;
+    for (uint32_t r = 0; r < sl.reqs.size(); ++r) {
+        const Request* q = sl.reqs[r];
+        if (q->type == kAppend && q->n) pieces.push_back({hp + item_off[r] * 4, (const char*)q->items, q->n * 4});
+    }
+    const size_t kParallelBytes = 16u << 20;
+    unsigned nt = std::thread::hardware_concurrency();
+    nt = std::max(1u, std::min(nt, 8u));
+    if (total_bytes < kParallelBytes || nt == 1) {
+        for (const Piece& p : pieces) memcpy(p.dst, p.src, p.bytes);
+        return;
+    }
+    // thread t copies bytes [t * share, (t + 1) * share) of the concatenation
+    const uint64_t share = (total_bytes + nt - 1) / nt;
+    auto work = [&](unsigned t) {
+        uint64_t lo = t * share, hi = std::min<uint64_t>(total_bytes, lo + share), pos = 0;
+        for (const Piece& p : pieces) {
+            const uint64_t a = std::max(lo, pos), b = std::min(hi, pos + p.bytes);
+            if (a < b) memcpy(p.dst + (a - pos), p.src + (a - pos), b - a);
+            pos += p.bytes;
+            if (pos >= hi) break;
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < nt; ++t) th.emplace_back(work, t);
+    work(0);
+    for (std::thread& x : th) x.join();
 }
 
 size_t query_bytes(uint32_t cap) { return (size_t)cap * sizeof(DevEntry) + 4 + sizeof(ServeQuery); }
@@ -313,10 +353,9 @@ int run_launch(pss_server* srv, uint32_t si) {
     if (rc != PSS_OK) return rc;
     char* dbase = (char*)sl.dev.ptr;
     char* hp = (char*)sl.pin;
-    for (uint32_t r = 0; r < sl.reqs.size(); ++r) {
-        Request* q = sl.reqs[r];
-        if (q->type == kAppend && q->n) memcpy(hp + item_off[r] * 4, q->items, q->n * 4);
-    }
+    const auto ts = Clock::now();
+    stage_items(sl, hp, item_off, items_total * 4);
+    const double stage = ms_between(ts, Clock::now());
     for (uint32_t i = 0; i < nb; ++i) hb[i].d.items = (const uint32_t*)(dbase + item_off[hb[i].req] * 4);
     char* hd = hp + it_b;
     for (uint32_t i = 0; i < nb; ++i) memcpy(hd + i * sizeof(BatchBlock), &hb[i].d, sizeof(BatchBlock));
@@ -325,6 +364,7 @@ int run_launch(pss_server* srv, uint32_t si) {
     if (!queries.empty()) memcpy(hd + bb + ndb + fb, queries.data(), queries.size() * sizeof(ServeQuery));
 
     hipStream_t st = sl.st;
+    if (hipEventRecord(sl.t0, st) != hipSuccess) return PSS_EDEVICE;
     // items and descriptors: two transfers from the pinned staging
     if ((it_b && hipMemcpyAsync(dbase, hp, it_b, hipMemcpyHostToDevice, st) != hipSuccess) ||
         hipMemcpyAsync(dbase + sl.off_desc, hd, sl.desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
@@ -367,7 +407,12 @@ int run_launch(pss_server* srv, uint32_t si) {
     if (rc == PSS_OK && sl.out_bytes &&
         hipMemcpyAsync(sl.pin, dbase + sl.off_out, sl.out_bytes, hipMemcpyDeviceToHost, st) != hipSuccess)
         rc = PSS_EDEVICE;
-    if (rc == PSS_OK && hipEventRecord(sl.done, st) != hipSuccess) rc = PSS_EDEVICE;
+    if (rc == PSS_OK && (hipEventRecord(sl.t1, st) != hipSuccess || hipEventRecord(sl.done, st) != hipSuccess))
+        rc = PSS_EDEVICE;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stage_ms += stage;
+    }
     sl.out_bytes = ob;  // entries part; counts follow at ob
     (void)nappend;
     return rc;
@@ -375,6 +420,8 @@ int run_launch(pss_server* srv, uint32_t si) {
 
 // Results of a finished launch into its requests (server lock held).
 void finish_launch(pss_server* srv, Slot& sl, int rc) {
+    float gms = 0.f;
+    if (rc == PSS_OK && hipEventElapsedTime(&gms, sl.t0, sl.t1) == hipSuccess) srv->gpu_ms += gms;
     const auto now = Clock::now();
     const char* base = (const char*)sl.pin;
     const uint32_t* counts = (const uint32_t*)(base + sl.out_bytes);
@@ -593,7 +640,8 @@ int pss_server_create(pss_ctx* ctx, uint32_t nsummaries, const uint32_t* h_ks, c
             if (rc != PSS_OK) break;
             // default priority streams
             if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+                hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreate(&sl.t0) != hipSuccess || hipEventCreate(&sl.t1) != hipSuccess)
                 rc = PSS_EDEVICE;
         }
         if (rc == PSS_OK) srv->worker = std::thread(server_loop, srv);
@@ -604,6 +652,8 @@ int pss_server_create(pss_ctx* ctx, uint32_t nsummaries, const uint32_t* h_ks, c
         for (Slot& sl : srv->slots) {
             if (sl.st) (void)hipStreamDestroy(sl.st);
             if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.t0) (void)hipEventDestroy(sl.t0);
+            if (sl.t1) (void)hipEventDestroy(sl.t1);
         }
         srv->pool_mem.release();
         delete srv;
@@ -628,6 +678,8 @@ void pss_server_destroy(pss_server* srv) {
         if (sl.pin) (void)hipHostFree(sl.pin);
         if (sl.st) (void)hipStreamDestroy(sl.st);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.t0) (void)hipEventDestroy(sl.t0);
+        if (sl.t1) (void)hipEventDestroy(sl.t1);
     }
     for (auto& kv : srv->live) delete kv.second;  // every submitted request not yet waited for
     srv->pool_mem.release();
@@ -706,6 +758,8 @@ int pss_server_stats(pss_server* srv, pss_server_stats_t* st) {
     st->max_launch_requests = srv->max_launch_requests;
     st->pending = (uint32_t)srv->pending.size();
     st->status = srv->fatal;
+    st->stage_ms = srv->stage_ms;
+    st->gpu_ms = srv->gpu_ms;
     return PSS_OK;
 }
 

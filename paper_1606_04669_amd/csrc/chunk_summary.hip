@@ -28,9 +28,12 @@
 // exactly while its count is m: counts never decrease, an evicted counter is
 // re-installed at m+1, and no counter can join level m after it is listed.
 //
-// The hash is linear probing over 4-slot buckets (32 bytes, read with two
-// 16-byte LDS loads); deleted entries become tombstones that later inserts
-// reuse, and the table is rebuilt when live plus tombstone slots pass 3/4.
+// The hash maps an item to two 4-slot buckets (32 bytes each, read with two
+// 16-byte loads) and keeps its entry in one of their 8 slots; a new item
+// takes a free slot of the emptier bucket, or of a 64-slot stash when both
+// are full (searched only while it holds entries).  Lookups cost one round
+// of four loads whatever the load, and a deleted entry simply becomes empty:
+// no probe chains, tombstones or rebuilds.
 #include <type_traits>
 
 #include "pss_device.h"
@@ -55,10 +58,10 @@ __device__ unsigned long long g_kstats[16];
 #define KSTAT_FLUSH()
 #endif
 
+// Table entry: key | tag << 32 with tag 0 = empty, counter index + 1 (below
+// 2^31) = live, kTagPend | lane = claimed by a lane during a window.
 constexpr uint32_t kTagEmpty = 0u;
-constexpr uint32_t kTagTomb = 0xFFFFFFFFu;
 constexpr uint32_t kTagPend = 0x80000000u;
-constexpr uint64_t kTombEntry = (uint64_t)kTagTomb << 32;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 // Block summary size written when a loop bound that the algorithm guarantees
 // is exceeded (an internal invariant failed): the host reports a device error
@@ -69,9 +72,39 @@ __device__ __forceinline__ uint64_t make_entry(uint32_t key, uint32_t tag) {
     return ((uint64_t)tag << 32) | key;
 }
 
-// Home bucket of an item: multiplicative hash scaled to nb buckets.
+// The two buckets of an item: multiplicative hashes scaled to nb buckets;
+// the second is moved to the neighbour of the first when they coincide.
 __device__ __forceinline__ uint32_t home_bucket(uint32_t x, uint32_t nb) {
     return (uint32_t)(((uint64_t)(x * 0x9E3779B1u) * nb) >> 32);
+}
+
+__device__ __forceinline__ uint32_t alt_bucket(uint32_t x, uint32_t nb, uint32_t b1) {
+    uint32_t h = x * 0x85EBCA77u;
+    h = (h << 15) | (h >> 17);
+    const uint32_t b2 = (uint32_t)(((uint64_t)(h * 0xC2B2AE3Du) * nb) >> 32);
+    return b2 != b1 ? b2 : (b1 + 1 == nb ? 0u : b1 + 1);
+}
+
+__device__ __forceinline__ bool live_tag(uint32_t tag) { return tag - 1u < 0x7FFFFFFFu; }
+
+// Slot masks of a 4-slot bucket (two uint4 = four key/tag pairs).
+__device__ __forceinline__ uint32_t match_mask(const uint4& a, const uint4& b, uint32_t x) {
+    return ((a.x == x && live_tag(a.y)) ? 1u : 0u) | ((a.z == x && live_tag(a.w)) ? 2u : 0u) |
+           ((b.x == x && live_tag(b.y)) ? 4u : 0u) | ((b.z == x && live_tag(b.w)) ? 8u : 0u);
+}
+
+__device__ __forceinline__ uint32_t pend_mask(const uint4& a, const uint4& b, uint32_t x) {
+    return ((a.x == x && (a.y & kTagPend)) ? 1u : 0u) | ((a.z == x && (a.w & kTagPend)) ? 2u : 0u) |
+           ((b.x == x && (b.y & kTagPend)) ? 4u : 0u) | ((b.z == x && (b.w & kTagPend)) ? 8u : 0u);
+}
+
+__device__ __forceinline__ uint32_t empty_mask(const uint4& a, const uint4& b) {
+    return (a.y == kTagEmpty ? 1u : 0u) | (a.w == kTagEmpty ? 2u : 0u) | (b.y == kTagEmpty ? 4u : 0u) |
+           (b.w == kTagEmpty ? 8u : 0u);
+}
+
+__device__ __forceinline__ uint32_t tag_at(const uint4& a, const uint4& b, uint32_t i) {
+    return i == 0 ? a.y : i == 1 ? a.w : i == 2 ? b.y : b.w;
 }
 
 // ---------------------------------------------------------------------------
@@ -418,16 +451,16 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
     uint32_t* vslot = (uint32_t*)(lds + L.off_vslot);
     uint32_t* vhpos = (uint32_t*)(lds + L.off_vhpos);
     uint32_t* hist = (uint32_t*)(lds + L.off_hist);
-    // rebuild the hash when live + tombstone slots pass 3/4 (always >= 65 empty)
-    const uint32_t tlimit = min(T - T / 4, T - 65);
+    const uint4* stash4 = tbl4 + T / 2;
 
-    for (uint32_t i = lane; i < T; i += kWave) table[i] = 0ull;
+    for (uint32_t i = lane; i < T + kStash; i += kWave) table[i] = 0ull;
     for (uint32_t i = lane; i < k; i += kWave) mark[i] = 0;
 
     // Wave-uniform state.  Every update goes through uniform() so the compiler
     // keeps it in scalar registers and every loop that contains wave-wide
     // operations (ballot, DPP, readlane, shuffles) has a uniform exit.
-    uint32_t size = 0, full = 0, tused = 0, failed = 0;
+    uint32_t size = 0, full = 0, failed = 0;
+    uint32_t stash_live = 0;  // live entries in the stash
     // minimum level: count m and its listed counters [list_ptr, list_len)
     uint32_t m = 0, list_len = 0, list_ptr = 0;
     uint32_t last_slow = 0;
@@ -458,33 +491,29 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
             KSTAT_ADD(10, 1);
         }
         const unsigned long long tw = KSTAT_NOW();
-        if (tused > tlimit) {
-            // drop tombstones: rebuild the hash from the live counters
-            KSTAT_ADD(8, 1);
-            wave_sync();
-            for (uint32_t i = lane; i < T; i += kWave) table[i] = 0ull;
-            wave_sync();
-            bool bad = false;
-            for (uint32_t s = lane; s < size; s += kWave) {
-                const uint32_t x = item[s];
-                uint32_t h = 4 * home_bucket(x, NB);
-                uint32_t steps = 0;
-                while (atomicCAS((unsigned long long*)&table[h], 0ull, (unsigned long long)make_entry(x, s + 1)) != 0ull) {
-                    h = (h + 1 == T) ? 0 : h + 1;
-                    if (++steps >= T) {
-                        bad = true;
-                        break;
-                    }
+        if (stash_live) {
+            // move stash entries back to a bucket with room (deletions free
+            // slots all the time); lane i handles stash slot i
+            const uint32_t si = T + lane;
+            const uint64_t e = table[si];
+            const uint32_t key = (uint32_t)e, tag = (uint32_t)(e >> 32);
+            const uint32_t s1 = home_bucket(key, NB), s2 = alt_bucket(key, NB, s1);
+            const uint4 q0 = tbl4[2 * s1], q1 = tbl4[2 * s1 + 1];
+            const uint4 q2 = tbl4[2 * s2], q3 = tbl4[2 * s2 + 1];
+            const uint32_t e1 = empty_mask(q0, q1), e2 = empty_mask(q2, q3);
+            bool moved = false;
+            if (live_tag(tag) && (e1 | e2)) {
+                const uint32_t dst = __builtin_popcount(e1) >= __builtin_popcount(e2)
+                                         ? 4 * s1 + (uint32_t)__builtin_ctz(e1)
+                                         : 4 * s2 + (uint32_t)__builtin_ctz(e2);
+                if (atomicCAS((unsigned long long*)&table[dst], 0ull, (unsigned long long)e) == 0ull) {
+                    table[si] = 0ull;
+                    hpos[tag - 1u] = (idx_t)dst;
+                    moved = true;
                 }
-                hpos[s] = (idx_t)h;
             }
+            stash_live = uniform(stash_live - popc64(ballot(moved)));
             wave_sync();
-            tused = size;
-            if (ballot(bad)) {
-                failed = 1;
-                continue;
-            }
-            KSTAT_ADD(7, KSTAT_NOW() - tw);
         }
 
         const uint32_t wl = (uint32_t)((end - pos) < kWave ? (end - pos) : kWave);
@@ -508,42 +537,35 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         const bool early = last_slow && full && list_ptr < list_len;
         if (early) fetch_victims();
 
-        // 1. look up against the state at window start, one 4-slot bucket per
-        //    step (branch-free inside a step); a miss inserts at the first free
-        //    (tombstone or empty) slot it passed
+        // 1. look up against the state at window start: the item's two buckets
+        //    (four 16-byte loads, branch-free), then the stash while it is used
         bool hit = false, miss = false, bad = false;
         uint32_t slot = 0, hp = kNone;
+        const uint32_t b1 = home_bucket(x, NB);
+        const uint32_t b2 = alt_bucket(x, NB, b1);
         {
-            uint32_t b = home_bucket(x, NB);
-            uint32_t steps = 0;
-            bool go = valid;
-            while (go) {
-                const uint4 q0 = tbl4[2 * b];
-                const uint4 q1 = tbl4[2 * b + 1];
-                // live tags are counter index + 1 in [1, 2^31): (tag - 1) < 2^31 - 1
-                const uint32_t em = (q0.y == kTagEmpty ? 1u : 0u) | (q0.w == kTagEmpty ? 2u : 0u) |
-                                    (q1.y == kTagEmpty ? 4u : 0u) | (q1.w == kTagEmpty ? 8u : 0u);
-                const uint32_t fm = em | (q0.y == kTagTomb ? 1u : 0u) | (q0.w == kTagTomb ? 2u : 0u) |
-                                    (q1.y == kTagTomb ? 4u : 0u) | (q1.w == kTagTomb ? 8u : 0u);
-                const uint32_t hm = ((q0.x == x && q0.y - 1u < 0x7FFFFFFFu) ? 1u : 0u) |
-                                    ((q0.z == x && q0.w - 1u < 0x7FFFFFFFu) ? 2u : 0u) |
-                                    ((q1.x == x && q1.y - 1u < 0x7FFFFFFFu) ? 4u : 0u) |
-                                    ((q1.z == x && q1.w - 1u < 0x7FFFFFFFu) ? 8u : 0u);
-                if (hp == kNone && fm != 0u) hp = 4 * b + (uint32_t)__builtin_ctz(fm);
-                const uint32_t tag = (hm & 1u) ? q0.y : (hm & 2u) ? q0.w : (hm & 4u) ? q1.y : q1.w;
-                hit = hm != 0u;
-                slot = tag - 1u;
-                miss = !hit && em != 0u;
-                b = (b + 1 == NB) ? 0 : b + 1;
-                ++steps;
-                bad = steps >= NB && !hit && !miss;  // the table always keeps empty slots
-                go = !hit && !miss && !bad;
+            const uint4 q0 = tbl4[2 * b1], q1 = tbl4[2 * b1 + 1];
+            const uint4 q2 = tbl4[2 * b2], q3 = tbl4[2 * b2 + 1];
+            const uint32_t h1 = match_mask(q0, q1, x), h2 = match_mask(q2, q3, x);
+            const uint32_t tag = h1 ? tag_at(q0, q1, (uint32_t)__builtin_ctz(h1))
+                                    : tag_at(q2, q3, (uint32_t)__builtin_ctz(h2 | 16u) & 3u);
+            hit = valid && (h1 | h2) != 0u;
+            slot = tag - 1u;
+        }
+        if (stash_live) {
+            for (uint32_t i = 0; i < kStash / 2; ++i) {
+                const uint4 e = stash4[i];
+                if (e.x == x && live_tag(e.y)) {
+                    hit = valid;
+                    slot = e.y - 1u;
+                }
+                if (e.z == x && live_tag(e.w)) {
+                    hit = valid;
+                    slot = e.w - 1u;
+                }
             }
         }
-        if (ballot(bad)) {
-            failed = 1;
-            continue;
-        }
+        miss = valid && !hit;
 
         const uint64_t missmask = ballot(miss);
         KSTAT_ADD(15, KSTAT_NOW() - tw);
@@ -560,41 +582,74 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
 
         // 2. group unmonitored items by value: one pending hash entry per value,
         //    tagged with the lowest lane holding it
-        bool took_empty = false;
+        const unsigned long long tp = KSTAT_NOW();
+        //    Each lane claims a free slot of its emptier bucket (else of the
+        //    stash) with a compare-and-swap; a lane that finds its value
+        //    already claimed lowers the claim's lane instead.  Only claims
+        //    happen in this phase, so every failed swap uses up a slot and the
+        //    loop ends within 8 + 64 rounds.
         if (miss) {
             const uint64_t mine = make_entry(x, kTagPend | lane);
-            uint32_t h = hp;
             uint32_t steps = 0;
             for (;;) {
-                uint64_t e = table[h];
-                uint32_t tag = (uint32_t)(e >> 32);
-                if (tag == kTagEmpty || tag == kTagTomb) {
-                    const uint64_t old = atomicCAS((unsigned long long*)&table[h], (unsigned long long)e,
-                                                   (unsigned long long)mine);
-                    if (old == e) {
-                        took_empty = tag == kTagEmpty;
-                        break;
+                const uint4 q0 = tbl4[2 * b1], q1 = tbl4[2 * b1 + 1];
+                const uint4 q2 = tbl4[2 * b2], q3 = tbl4[2 * b2 + 1];
+                const uint32_t p1 = pend_mask(q0, q1, x), p2 = pend_mask(q2, q3, x);
+                uint32_t h = kNone;
+                bool join = false;
+                if (p1 | p2) {
+                    h = p1 ? 4 * b1 + (uint32_t)__builtin_ctz(p1) : 4 * b2 + (uint32_t)__builtin_ctz(p2);
+                    join = true;
+                } else {
+                    const uint32_t e1 = empty_mask(q0, q1), e2 = empty_mask(q2, q3);
+                    if (e1 | e2) {
+                        h = __builtin_popcount(e1) >= __builtin_popcount(e2) ? 4 * b1 + (uint32_t)__builtin_ctz(e1)
+                                                                             : 4 * b2 + (uint32_t)__builtin_ctz(e2);
+                    } else {
+                        // both buckets full: the value's claim, or a free slot, in the stash
+                        uint32_t fe = kNone;
+                        for (uint32_t i = 0; i < kStash / 2; ++i) {
+                            const uint4 e = stash4[i];
+                            if (e.x == x && (e.y & kTagPend)) {
+                                h = T + 2 * i;
+                                join = true;
+                            }
+                            if (e.z == x && (e.w & kTagPend)) {
+                                h = T + 2 * i + 1;
+                                join = true;
+                            }
+                            if (fe == kNone && e.y == kTagEmpty) fe = T + 2 * i;
+                            if (fe == kNone && e.w == kTagEmpty) fe = T + 2 * i + 1;
+                        }
+                        if (!join) h = fe;
                     }
-                    e = old;
-                    tag = (uint32_t)(old >> 32);
                 }
-                if (tag != kTagTomb && (tag & kTagPend) && (uint32_t)e == x) {
-                    atomicMin(((uint32_t*)&table[h]) + 1, kTagPend | lane);
+                if (h == kNone) {  // no free slot anywhere
+                    bad = true;
                     break;
                 }
-                h = (h + 1 == T) ? 0 : h + 1;
-                if (++steps >= T) {
+                if (join) {
+                    atomicMin(((uint32_t*)&table[h]) + 1, kTagPend | lane);
+                    hp = h;
+                    break;
+                }
+                if (atomicCAS((unsigned long long*)&table[h], 0ull, (unsigned long long)mine) == 0ull) {
+                    hp = h;
+                    break;
+                }
+                if (++steps > 8 + kStash) {
                     bad = true;
                     break;
                 }
             }
-            hp = h;
         }
         if (ballot(bad)) {
             failed = 1;
             continue;
         }
 
+        KSTAT_ADD(13, KSTAT_NOW() - tp);
+        const unsigned long long tv = KSTAT_NOW();
         // 3. victims: the counters of level m in id order, from the list
         uint32_t avail = 0, vr = 0;
         uint64_t vmask = 0;
@@ -656,6 +711,7 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
             }
         }
         wave_sync();
+        KSTAT_ADD(6, KSTAT_NOW() - tv);
 
         const uint32_t rep = miss ? (((const volatile uint32_t*)&table[hp])[1] & 63u) : lane;
         const uint32_t jmark = (hit && full) ? mark[slot] : 0u;
@@ -663,7 +719,6 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         const bool newf = (newmask >> lane) & 1ull;
         const uint32_t r = popc64(newmask);
         const uint32_t nrank = mbcnt(newmask);
-        tused = uniform(tused + popc64(ballot(took_empty)));
 
         // 4. longest prefix with no conflict
         uint32_t cpos = wl;
@@ -692,7 +747,7 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                     err[myslot] = 0u;
                 } else {
                     myslot = vslot[nrank];
-                    table[vhpos[nrank]] = kTombEntry;
+                    table[vhpos[nrank]] = 0ull;  // the victim's entry becomes empty
                     cnt[myslot] = m + 1u;
                     err[myslot] = m;
                 }
@@ -700,7 +755,7 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                 hpos[myslot] = (idx_t)hp;
                 table[hp] = make_entry(x, myslot + 1u);
             } else {
-                table[hp] = kTombEntry;  // not applied: retire the pending entry
+                table[hp] = 0ull;  // not applied: release the claim
             }
         }
         const bool repeat = in && miss && !newf;
@@ -713,6 +768,10 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
 
         const uint64_t inmask = (p >= kWave) ? ~0ull : ((1ull << p) - 1ull);
         const uint32_t rp = popc64(newmask & inmask);
+        // stash occupancy: applied new items placed there, evicted victims removed from there
+        const uint32_t sadd = popc64(ballot(newf && in && hp >= T));
+        const uint32_t sdel = popc64(ballot(vv && vr < rp && vhp >= T));
+        stash_live = uniform(stash_live + sadd - sdel);
         if (!full) {
             size = uniform(size + rp);
             if (size == k) {

@@ -20,6 +20,8 @@ constexpr uint32_t kRingHalf = 512;
 constexpr uint32_t kRing = 2 * kRingHalf;
 // Largest hash table whose slot positions fit uint16 (LDS-resident state).
 constexpr uint32_t kMaxLdsTableSlots = 65536;
+// Overflow slots after the buckets, for items whose two buckets are full.
+constexpr uint32_t kStash = 64;
 
 PSS_HD inline uint32_t next_pow2(uint32_t v) {
     uint32_t p = 1;
@@ -43,7 +45,7 @@ PSS_HD inline uint32_t sort_lanes_per_k(uint32_t k) {
 struct ChunkLayout {
     uint32_t k;
     uint32_t nbuckets;      // hash buckets of 4 slots
-    uint32_t tsize;         // 4 * nbuckets slots
+    uint32_t tsize;         // 4 * nbuckets slots (the stash follows them)
     uint32_t global_state;  // 1: state in global memory, 32-bit indices; 0: LDS, 16-bit indices
     // state offsets (bytes from the state base)
     uint32_t off_table, off_cnt, off_item, off_err, off_hpos, off_list, off_mark, off_tkey, off_list2, off_tkey2;
@@ -70,7 +72,7 @@ struct ChunkLayout {
         L.tsize = 4 * L.nbuckets;
         const uint32_t idx = global_state ? 4u : 2u;
         uint32_t o = 0;
-        L.off_table = o; o = align16(o + 8 * L.tsize);   // uint64 entries (key | tag << 32), 32 B buckets
+        L.off_table = o; o = align16(o + 8 * (L.tsize + kStash));  // uint64 entries (key | tag << 32): 32-B buckets, then the stash
         L.off_cnt = o;   o = align16(o + 4 * k);
         L.off_item = o;  o = align16(o + 4 * k);
         L.off_err = o;   o = align16(o + 4 * k);
@@ -94,7 +96,7 @@ struct ChunkLayout {
         return L;
     }
 
-    PSS_HD bool fits_lds_indices() const { return tsize <= kMaxLdsTableSlots && k <= 65535u; }
+    PSS_HD bool fits_lds_indices() const { return tsize + kStash <= kMaxLdsTableSlots && k <= 65535u; }
 };
 
 }  // namespace pss

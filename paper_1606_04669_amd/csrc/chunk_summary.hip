@@ -28,8 +28,8 @@
 // exactly while its count is m: counts never decrease, an evicted counter is
 // re-installed at m+1, and no counter can join level m after it is listed.
 //
-// The hash maps an item to two 4-slot buckets (32 bytes each, read with two
-// 16-byte loads) and keeps its entry in one of their 8 slots; a new item
+// The hash maps an item to two 8-slot buckets (64 bytes each, read with four
+// 16-byte loads) and keeps its entry in one of their 16 slots; a new item
 // takes a free slot of the emptier bucket, or of a 64-slot stash when both
 // are full (searched only while it holds entries).  Lookups cost one round
 // of four loads whatever the load, and a deleted entry simply becomes empty:
@@ -44,13 +44,13 @@ namespace pss {
 
 #ifdef PSS_KERNEL_STATS
 // analysis builds only: per-phase cycle and event counts summed over waves
-__device__ unsigned long long g_kstats[16];
-#define KSTAT_DECL unsigned long long ks_[16] = {0};
+__device__ unsigned long long g_kstats[24];
+#define KSTAT_DECL unsigned long long ks_[24] = {0};
 #define KSTAT_ADD(i, v) (ks_[(i)] += (unsigned long long)(v))
 #define KSTAT_NOW() ((unsigned long long)clock64())
 #define KSTAT_FLUSH()                                                        \
     if (lane == 0)                                                           \
-        for (int i_ = 0; i_ < 16; ++i_) atomicAdd(&g_kstats[i_], ks_[i_]);
+        for (int i_ = 0; i_ < 24; ++i_) atomicAdd(&g_kstats[i_], ks_[i_]);
 #else
 #define KSTAT_DECL
 #define KSTAT_ADD(i, v) ((void)0)
@@ -87,24 +87,73 @@ __device__ __forceinline__ uint32_t alt_bucket(uint32_t x, uint32_t nb, uint32_t
 
 __device__ __forceinline__ bool live_tag(uint32_t tag) { return tag - 1u < 0x7FFFFFFFu; }
 
-// Slot masks of a 4-slot bucket (two uint4 = four key/tag pairs).
-__device__ __forceinline__ uint32_t match_mask(const uint4& a, const uint4& b, uint32_t x) {
-    return ((a.x == x && live_tag(a.y)) ? 1u : 0u) | ((a.z == x && live_tag(a.w)) ? 2u : 0u) |
-           ((b.x == x && live_tag(b.y)) ? 4u : 0u) | ((b.z == x && live_tag(b.w)) ? 8u : 0u);
+// One bucket: kBucketSlots key/tag pairs, read with kBucketSlots / 2
+// 16-byte loads.
+constexpr int kBucketQuads = (int)kBucketSlots / 2;
+struct Bucket {
+    uint4 q[kBucketQuads];
+};
+
+__device__ __forceinline__ Bucket load_bucket(const uint4* tbl4, uint32_t b) {
+    Bucket r;
+#pragma unroll
+    for (int i = 0; i < kBucketQuads; ++i) r.q[i] = tbl4[kBucketQuads * b + i];
+    return r;
 }
 
-__device__ __forceinline__ uint32_t pend_mask(const uint4& a, const uint4& b, uint32_t x) {
-    return ((a.x == x && (a.y & kTagPend)) ? 1u : 0u) | ((a.z == x && (a.w & kTagPend)) ? 2u : 0u) |
-           ((b.x == x && (b.y & kTagPend)) ? 4u : 0u) | ((b.z == x && (b.w & kTagPend)) ? 8u : 0u);
+// Slot masks (bit i = slot i of the bucket).
+__device__ __forceinline__ uint32_t match_mask(const Bucket& B, uint32_t x) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < kBucketQuads; ++i) {
+        m |= ((B.q[i].x == x && live_tag(B.q[i].y)) ? 1u : 0u) << (2 * i);
+        m |= ((B.q[i].z == x && live_tag(B.q[i].w)) ? 1u : 0u) << (2 * i + 1);
+    }
+    return m;
 }
 
-__device__ __forceinline__ uint32_t empty_mask(const uint4& a, const uint4& b) {
-    return (a.y == kTagEmpty ? 1u : 0u) | (a.w == kTagEmpty ? 2u : 0u) | (b.y == kTagEmpty ? 4u : 0u) |
-           (b.w == kTagEmpty ? 8u : 0u);
+__device__ __forceinline__ uint32_t pend_mask(const Bucket& B, uint32_t x) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < kBucketQuads; ++i) {
+        m |= ((B.q[i].x == x && (B.q[i].y & kTagPend)) ? 1u : 0u) << (2 * i);
+        m |= ((B.q[i].z == x && (B.q[i].w & kTagPend)) ? 1u : 0u) << (2 * i + 1);
+    }
+    return m;
 }
 
-__device__ __forceinline__ uint32_t tag_at(const uint4& a, const uint4& b, uint32_t i) {
-    return i == 0 ? a.y : i == 1 ? a.w : i == 2 ? b.y : b.w;
+__device__ __forceinline__ uint32_t empty_mask(const Bucket& B) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < kBucketQuads; ++i) {
+        m |= (B.q[i].y == kTagEmpty ? 1u : 0u) << (2 * i);
+        m |= (B.q[i].w == kTagEmpty ? 1u : 0u) << (2 * i + 1);
+    }
+    return m;
+}
+
+// The free slot an item claims in a bucket with free-slot mask e (nonzero):
+// the (h mod popcount(e))-th free slot for a hash h of the item, so that
+// equal items pick the same slot and different items spread over the free
+// ones.
+__device__ __forceinline__ uint32_t pick_free(uint32_t e, uint32_t x) {
+    const uint32_t n = (uint32_t)__builtin_popcount(e);
+    uint32_t r = (((x * 0x2C1B3C6Du) >> 16) * n) >> 16;  // in [0, n)
+    for (uint32_t i = 0; i < kBucketSlots; ++i) {  // drop the r lowest set bits
+        const bool go = i < r;
+        e = go ? (e & (e - 1u)) : e;
+    }
+    return (uint32_t)__builtin_ctz(e);
+}
+
+__device__ __forceinline__ uint32_t tag_at(const Bucket& B, uint32_t i) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int j = 0; j < kBucketQuads; ++j) {
+        t = (i == 2u * j) ? B.q[j].y : t;
+        t = (i == 2u * j + 1) ? B.q[j].w : t;
+    }
+    return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -188,6 +237,21 @@ __device__ void sort_level_dispatch(uint16_t* list, const uint32_t* item, uint32
     }
 }
 
+#ifdef PSS_KERNEL_STATS
+#define SORT_T(i) unsigned long long st_##i = clock64();
+#define SORT_FLUSH()                                   \
+    if (lane == 0) {                                   \
+        atomicAdd(&g_kstats[19], st_1 - st_0);         \
+        atomicAdd(&g_kstats[20], st_2 - st_1);         \
+        atomicAdd(&g_kstats[21], st_3 - st_2);         \
+        atomicAdd(&g_kstats[22], st_4 - st_3);         \
+        atomicAdd(&g_kstats[23], st_5 - st_4);         \
+    }
+#else
+#define SORT_T(i)
+#define SORT_FLUSH()
+#endif
+
 // Largest bucket the bucketed sort ranks directly; beyond it the level is
 // sorted with the register network instead.
 constexpr uint32_t kMaxBucket = 48;
@@ -202,6 +266,7 @@ __device__ bool sort_level_buckets(uint16_t* list, const uint32_t* item, uint32_
                                    uint32_t len, uint32_t lane) {
     uint32_t sd[P], id[P], pin[P];
     uint32_t orv = 0u, andv = 0xFFFFFFFFu;
+    SORT_T(0);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
         const uint32_t g = lane * P + j;
@@ -213,6 +278,7 @@ __device__ bool sort_level_buckets(uint16_t* list, const uint32_t* item, uint32_
             andv &= id[j];
         }
     }
+    SORT_T(1);
     const uint32_t diff = wave_or_u32(orv) ^ wave_and_u32(andv);
     const uint32_t hb = 31u - (uint32_t)__builtin_clz(diff | 1u);
     const uint32_t shift = hb >= 7u ? hb - 7u : 0u;
@@ -226,6 +292,7 @@ __device__ bool sort_level_buckets(uint16_t* list, const uint32_t* item, uint32_
         pin[j] = (g < len) ? atomicAdd(&hist[d], 1u) : 0u;
     }
     wave_sync();
+    SORT_T(2);
     const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
     if (wave_max_u32(max(max(h0, h1), max(h2, h3))) > kMaxBucket) return false;
     // exclusive scan of the 256 counts: bucket d occupies [hist[d], hist[d+1])
@@ -249,6 +316,7 @@ __device__ bool sort_level_buckets(uint16_t* list, const uint32_t* item, uint32_
         if (g < len) tkey[hist[sd[j] >> 16] + pin[j]] = id[j];
     }
     wave_sync();
+    SORT_T(3);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
         const uint32_t g = lane * P + j;
@@ -261,11 +329,14 @@ __device__ bool sort_level_buckets(uint16_t* list, const uint32_t* item, uint32_
         }
     }
     wave_sync();
+    SORT_T(4);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
         const uint32_t g = lane * P + j;
         if (g < len) list[pin[j]] = (uint16_t)(sd[j] & 0xFFFFu);
     }
+    SORT_T(5);
+    SORT_FLUSH();
     return true;
 }
 
@@ -498,14 +569,13 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
             const uint64_t e = table[si];
             const uint32_t key = (uint32_t)e, tag = (uint32_t)(e >> 32);
             const uint32_t s1 = home_bucket(key, NB), s2 = alt_bucket(key, NB, s1);
-            const uint4 q0 = tbl4[2 * s1], q1 = tbl4[2 * s1 + 1];
-            const uint4 q2 = tbl4[2 * s2], q3 = tbl4[2 * s2 + 1];
-            const uint32_t e1 = empty_mask(q0, q1), e2 = empty_mask(q2, q3);
+            const Bucket B1 = load_bucket(tbl4, s1), B2 = load_bucket(tbl4, s2);
+            const uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2);
             bool moved = false;
             if (live_tag(tag) && (e1 | e2)) {
                 const uint32_t dst = __builtin_popcount(e1) >= __builtin_popcount(e2)
-                                         ? 4 * s1 + (uint32_t)__builtin_ctz(e1)
-                                         : 4 * s2 + (uint32_t)__builtin_ctz(e2);
+                                         ? kBucketSlots * s1 + (uint32_t)__builtin_ctz(e1)
+                                         : kBucketSlots * s2 + (uint32_t)__builtin_ctz(e2);
                 if (atomicCAS((unsigned long long*)&table[dst], 0ull, (unsigned long long)e) == 0ull) {
                     table[si] = 0ull;
                     hpos[tag - 1u] = (idx_t)dst;
@@ -538,20 +608,21 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         if (early) fetch_victims();
 
         // 1. look up against the state at window start: the item's two buckets
-        //    (four 16-byte loads, branch-free), then the stash while it is used
+        //    (eight 16-byte loads, branch-free), then the stash while it is used
         bool hit = false, miss = false, bad = false;
         uint32_t slot = 0, hp = kNone;
         const uint32_t b1 = home_bucket(x, NB);
         const uint32_t b2 = alt_bucket(x, NB, b1);
+        Bucket B1 = load_bucket(tbl4, b1), B2 = load_bucket(tbl4, b2);
         {
-            const uint4 q0 = tbl4[2 * b1], q1 = tbl4[2 * b1 + 1];
-            const uint4 q2 = tbl4[2 * b2], q3 = tbl4[2 * b2 + 1];
-            const uint32_t h1 = match_mask(q0, q1, x), h2 = match_mask(q2, q3, x);
-            const uint32_t tag = h1 ? tag_at(q0, q1, (uint32_t)__builtin_ctz(h1))
-                                    : tag_at(q2, q3, (uint32_t)__builtin_ctz(h2 | 16u) & 3u);
+            const uint32_t h1 = match_mask(B1, x), h2 = match_mask(B2, x);
+            const uint32_t tag = h1 ? tag_at(B1, (uint32_t)__builtin_ctz(h1))
+                                    : tag_at(B2, (uint32_t)__builtin_ctz(h2 | (1u << kBucketSlots)) &
+                                                     (kBucketSlots - 1));
             hit = valid && (h1 | h2) != 0u;
             slot = tag - 1u;
         }
+        KSTAT_ADD(16, stash_live ? 1 : 0);
         if (stash_live) {
             for (uint32_t i = 0; i < kStash / 2; ++i) {
                 const uint4 e = stash4[i];
@@ -587,24 +658,28 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         //    stash) with a compare-and-swap; a lane that finds its value
         //    already claimed lowers the claim's lane instead.  Only claims
         //    happen in this phase, so every failed swap uses up a slot and the
-        //    loop ends within 8 + 64 rounds.
+        //    loop ends within 16 + 64 rounds.
+        //    The first round uses the lookup's reads: no claim exists yet.
         if (miss) {
             const uint64_t mine = make_entry(x, kTagPend | lane);
             uint32_t steps = 0;
             for (;;) {
-                const uint4 q0 = tbl4[2 * b1], q1 = tbl4[2 * b1 + 1];
-                const uint4 q2 = tbl4[2 * b2], q3 = tbl4[2 * b2 + 1];
-                const uint32_t p1 = pend_mask(q0, q1, x), p2 = pend_mask(q2, q3, x);
+                if (steps) {
+                    B1 = load_bucket(tbl4, b1);
+                    B2 = load_bucket(tbl4, b2);
+                }
+                const uint32_t p1 = pend_mask(B1, x), p2 = pend_mask(B2, x);
                 uint32_t h = kNone;
                 bool join = false;
                 if (p1 | p2) {
-                    h = p1 ? 4 * b1 + (uint32_t)__builtin_ctz(p1) : 4 * b2 + (uint32_t)__builtin_ctz(p2);
+                    h = p1 ? kBucketSlots * b1 + (uint32_t)__builtin_ctz(p1)
+                           : kBucketSlots * b2 + (uint32_t)__builtin_ctz(p2);
                     join = true;
                 } else {
-                    const uint32_t e1 = empty_mask(q0, q1), e2 = empty_mask(q2, q3);
+                    const uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2);
                     if (e1 | e2) {
-                        h = __builtin_popcount(e1) >= __builtin_popcount(e2) ? 4 * b1 + (uint32_t)__builtin_ctz(e1)
-                                                                             : 4 * b2 + (uint32_t)__builtin_ctz(e2);
+                        h = __builtin_popcount(e1) >= __builtin_popcount(e2) ? kBucketSlots * b1 + pick_free(e1, x)
+                                                                             : kBucketSlots * b2 + pick_free(e2, x);
                     } else {
                         // both buckets full: the value's claim, or a free slot, in the stash
                         uint32_t fe = kNone;
@@ -637,7 +712,7 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                     hp = h;
                     break;
                 }
-                if (++steps > 8 + kStash) {
+                if (++steps > 2 * kBucketSlots + kStash) {
                     bad = true;
                     break;
                 }
@@ -647,6 +722,8 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
             failed = 1;
             continue;
         }
+        KSTAT_ADD(17, popc64(ballot(miss && hp >= T)));
+        KSTAT_ADD(18, popc64(ballot(miss)));
 
         KSTAT_ADD(13, KSTAT_NOW() - tp);
         const unsigned long long tv = KSTAT_NOW();
@@ -674,18 +751,49 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                     // level exhausted: list the new minimum level, by id
                     const unsigned long long tl = KSTAT_NOW();
                     KSTAT_ADD(5, 1);
-                    uint32_t mn = 0xFFFFFFFFu;
-                    for (uint32_t s = lane; s < k; s += kWave) mn = min(mn, cnt[s]);
+                    // one pass finds the minimum and collects the counters at
+                    // m + 1, the usual next level; a second pass collects the
+                    // true minimum level when it differs
+                    const uint32_t guess = m + 1u;
+                    uint32_t mn = 0xFFFFFFFFu, len = 0;
+                    for (uint32_t b = 0; b < k; b += 4 * kWave) {
+                        uint32_t cv[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const uint32_t s = b + j * kWave + lane;
+                            cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
+                        }
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            mn = min(mn, cv[j]);
+                            const bool take = cv[j] == guess;
+                            const uint64_t bm = ballot(take);
+                            if (take) list[len + mbcnt(bm)] = (idx_t)(b + j * kWave + lane);
+                            len = uniform(len + popc64(bm));
+                        }
+                    }
                     m = uniform(wave_min_u32(mn));
-                    uint32_t len = 0;
-                    for (uint32_t b = 0; b < k; b += kWave) {
-                        const uint32_t s = b + lane;
-                        const bool take = s < k && cnt[s] == m;
-                        const uint64_t bm = ballot(take);
-                        if (take) list[len + mbcnt(bm)] = (idx_t)s;
-                        len = uniform(len + popc64(bm));
+                    if (m != guess) {
+                        len = 0;
+                        for (uint32_t b = 0; b < k; b += 4 * kWave) {
+                            uint32_t cv[4];
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const uint32_t s = b + j * kWave + lane;
+                                cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
+                            }
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const bool take = cv[j] == m;
+                                const uint64_t bm = ballot(take);
+                                if (take) list[len + mbcnt(bm)] = (idx_t)(b + j * kWave + lane);
+                                len = uniform(len + popc64(bm));
+                            }
+                        }
                     }
                     wave_sync();
+                    KSTAT_ADD(7, KSTAT_NOW() - tl);
+                    const unsigned long long tsrt = KSTAT_NOW();
                     if constexpr (G) {
                         if (len <= 64)
                             sort_level_rank<idx_t>(list, item, len, lane);
@@ -697,6 +805,7 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                     }
                     list_len = len;
                     list_ptr = 0;
+                    KSTAT_ADD(8, KSTAT_NOW() - tsrt);
                     KSTAT_ADD(4, KSTAT_NOW() - tl);
                 }
                 fetch_victims();
@@ -916,7 +1025,7 @@ hipError_t launch_batch_blocks(const BatchBlock* blocks, uint32_t nblocks, uint3
 extern "C" int pss_debug_kstats(unsigned long long* out, int reset) {
     if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_kstats), sizeof(g_kstats)) != hipSuccess) return -6;
     if (reset) {
-        unsigned long long z[16] = {0};
+        unsigned long long z[24] = {0};
         if (hipMemcpyToSymbol(HIP_SYMBOL(g_kstats), z, sizeof(z)) != hipSuccess) return -6;
     }
     return 0;

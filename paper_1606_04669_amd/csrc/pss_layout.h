@@ -20,6 +20,17 @@ constexpr uint32_t kRingHalf = 512;
 constexpr uint32_t kRing = 2 * kRingHalf;
 // Largest hash table whose slot positions fit uint16 (LDS-resident state).
 constexpr uint32_t kMaxLdsTableSlots = 65536;
+// Slots per hash bucket (key/tag pairs of 8 bytes).
+#ifndef PSS_BUCKET_SLOTS
+#define PSS_BUCKET_SLOTS 8
+#endif
+constexpr uint32_t kBucketSlots = PSS_BUCKET_SLOTS;
+#ifndef PSS_SLOTS_X16
+#define PSS_SLOTS_X16 32
+#endif
+#ifndef PSS_SLOTS_X16_SMALLK
+#define PSS_SLOTS_X16_SMALLK PSS_SLOTS_X16
+#endif
 // Overflow slots after the buckets, for items whose two buckets are full.
 constexpr uint32_t kStash = 64;
 
@@ -44,8 +55,8 @@ PSS_HD inline uint32_t sort_lanes_per_k(uint32_t k) {
 
 struct ChunkLayout {
     uint32_t k;
-    uint32_t nbuckets;      // hash buckets of 4 slots
-    uint32_t tsize;         // 4 * nbuckets slots (the stash follows them)
+    uint32_t nbuckets;      // hash buckets of kBucketSlots slots
+    uint32_t tsize;         // kBucketSlots * nbuckets slots (the stash follows them)
     uint32_t global_state;  // 1: state in global memory, 32-bit indices; 0: LDS, 16-bit indices
     // state offsets (bytes from the state base)
     uint32_t off_table, off_cnt, off_item, off_err, off_hpos, off_list, off_mark, off_tkey, off_list2, off_tkey2;
@@ -54,9 +65,9 @@ struct ChunkLayout {
     uint32_t off_ring, off_vslot, off_vhpos, off_hist;
     uint32_t lds_bytes;
 
-    // Default hash slots per counter (x16): more room (shorter probes, fewer
-    // rebuilds) while the footprint is small, 2 per counter for large k.
-    PSS_HD static uint32_t default_slots_x16(uint32_t k) { return k <= 1024 ? 64 : 32; }
+    // Default hash slots per counter (x16): 2 per counter keeps the two-choice
+    // table at most half full (plus a window's claims).
+    PSS_HD static uint32_t default_slots_x16(uint32_t k) { return k <= 1024 ? PSS_SLOTS_X16_SMALLK : PSS_SLOTS_X16; }
 
     // slots_per_counter_x16: hash slots per counter (x16), a speed / memory
     // knob that never changes results (0 = default).  global_state selects
@@ -68,11 +79,11 @@ struct ChunkLayout {
         if (slots_per_counter_x16 == 0) slots_per_counter_x16 = default_slots_x16(k);
         uint32_t slots = (uint32_t)(((uint64_t)k * slots_per_counter_x16 + 15) / 16);
         if (slots < 256) slots = 256;
-        L.nbuckets = (slots + 3) / 4;
-        L.tsize = 4 * L.nbuckets;
+        L.nbuckets = (slots + kBucketSlots - 1) / kBucketSlots;
+        L.tsize = kBucketSlots * L.nbuckets;
         const uint32_t idx = global_state ? 4u : 2u;
         uint32_t o = 0;
-        L.off_table = o; o = align16(o + 8 * (L.tsize + kStash));  // uint64 entries (key | tag << 32): 32-B buckets, then the stash
+        L.off_table = o; o = align16(o + 8 * (L.tsize + kStash));  // uint64 entries (key | tag << 32): 64-B buckets, then the stash
         L.off_cnt = o;   o = align16(o + 4 * k);
         L.off_item = o;  o = align16(o + 4 * k);
         L.off_err = o;   o = align16(o + 4 * k);

@@ -468,22 +468,22 @@ __device__ __forceinline__ uint4 load4(const uint32_t* __restrict__ items, uint6
     return v;
 }
 
+// One half of the ring: 256 items, four per lane.
+static_assert(kRingHalf == 4 * kWave, "one uint4 per lane per ring half");
 struct Prefetch {
-    uint4 a, b;
+    uint4 a;
 };
 
 __device__ __forceinline__ Prefetch fetch_half(const uint32_t* __restrict__ items, uint64_t tile, uint64_t n,
                                                uint64_t stop, int vec_ok, uint32_t lane) {
     Prefetch p;
     p.a = load4(items, tile + 4 * lane, n, stop, vec_ok);
-    p.b = load4(items, tile + 256 + 4 * lane, n, stop, vec_ok);
     return p;
 }
 
 __device__ __forceinline__ void store_half(uint32_t* ring, uint64_t tile, const Prefetch& p, uint32_t lane) {
     uint32_t base = (uint32_t)tile & (kRing - 1);
     *(uint4*)(ring + base + 4 * lane) = p.a;
-    *(uint4*)(ring + base + 256 + 4 * lane) = p.b;
 }
 
 // ---------------------------------------------------------------------------
@@ -510,8 +510,8 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
     uint64_t* table = (uint64_t*)(sb + L.off_table);
     const uint4* tbl4 = (const uint4*)(sb + L.off_table);
     uint32_t* cnt = (uint32_t*)(sb + L.off_cnt);
-    uint32_t* item = (uint32_t*)(sb + L.off_item);
-    uint32_t* err = (uint32_t*)(sb + L.off_err);
+    uint32_t* item = o_item;  // ids and errors live in the output arrays
+    uint32_t* err = o_err;
     idx_t* hpos = (idx_t*)(sb + L.off_hpos);
     idx_t* list = (idx_t*)(sb + L.off_list);
     uint8_t* mark = (uint8_t*)(sb + L.off_mark);
@@ -521,7 +521,9 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
     uint32_t* ring = (uint32_t*)(lds + L.off_ring);
     uint32_t* vslot = (uint32_t*)(lds + L.off_vslot);
     uint32_t* vhpos = (uint32_t*)(lds + L.off_vhpos);
-    uint32_t* hist = (uint32_t*)(lds + L.off_hist);
+    // the sort histogram: in LDS beside the ring (HBM state) or over the
+    // victim marks (LDS state)
+    uint32_t* hist = G ? (uint32_t*)(lds + L.off_hist) : (uint32_t*)(sb + L.off_hist);
     const uint4* stash4 = tbl4 + T / 2;
 
     for (uint32_t i = lane; i < T + kStash; i += kWave) table[i] = 0ull;
@@ -802,6 +804,9 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                         wave_sync();
                     } else {
                         sort_level<P>(list, item, tkey, hist, len, lane);
+                        // the histogram overlaid the victim marks: zero them again
+                        for (uint32_t i = 4 * lane; i < kHistBytes; i += 4 * kWave) *(uint32_t*)(mark + i) = 0u;
+                        wave_sync();
                     }
                     list_len = len;
                     list_ptr = 0;
@@ -916,11 +921,7 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         for (uint32_t s = lane; s < k; s += kWave) mn = min(mn, cnt[s]);
         mo = wave_min_u32(mn);
     }
-    for (uint32_t s = lane; s < size; s += kWave) {
-        o_item[s] = item[s];
-        o_cnt[s] = cnt[s];
-        o_err[s] = err[s];
-    }
+    for (uint32_t s = lane; s < size; s += kWave) o_cnt[s] = cnt[s];  // ids and errors are in place
     if (lane == 0) {
         *o_size = size;
         *o_min = mo;

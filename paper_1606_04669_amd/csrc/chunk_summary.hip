@@ -112,16 +112,6 @@ __device__ __forceinline__ uint32_t match_mask(const Bucket& B, uint32_t x) {
     return m;
 }
 
-__device__ __forceinline__ uint32_t pend_mask(const Bucket& B, uint32_t x) {
-    uint32_t m = 0;
-#pragma unroll
-    for (int i = 0; i < kBucketQuads; ++i) {
-        m |= ((B.q[i].x == x && (B.q[i].y & kTagPend)) ? 1u : 0u) << (2 * i);
-        m |= ((B.q[i].z == x && (B.q[i].w & kTagPend)) ? 1u : 0u) << (2 * i + 1);
-    }
-    return m;
-}
-
 __device__ __forceinline__ uint32_t empty_mask(const Bucket& B) {
     uint32_t m = 0;
 #pragma unroll
@@ -657,60 +647,61 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         //    tagged with the lowest lane holding it
         const unsigned long long tp = KSTAT_NOW();
         //    Each lane claims a free slot of its emptier bucket (else of the
-        //    stash) with a compare-and-swap; a lane that finds its value
-        //    already claimed lowers the claim's lane instead.  Only claims
-        //    happen in this phase, so every failed swap uses up a slot and the
-        //    loop ends within 16 + 64 rounds.
-        //    The first round uses the lookup's reads: no claim exists yet.
+        //    stash) with a compare-and-swap, working from the buckets as the
+        //    lookup read them: no claim exists at window start, and a lost
+        //    swap returns the slot's new entry -- a claim of the same value
+        //    (the lane joins it, lowering the claim's lane) or of another one
+        //    (the slot leaves the lane's view).  Lanes holding equal values
+        //    see the same buckets and the same outcomes, so they pick the same
+        //    slots.  Every lost swap removes a slot from the view, so the loop
+        //    ends within 16 + 64 rounds.
         if (miss) {
             const uint64_t mine = make_entry(x, kTagPend | lane);
+            uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2);
             uint32_t steps = 0;
             for (;;) {
-                if (steps) {
-                    B1 = load_bucket(tbl4, b1);
-                    B2 = load_bucket(tbl4, b2);
-                }
-                const uint32_t p1 = pend_mask(B1, x), p2 = pend_mask(B2, x);
                 uint32_t h = kNone;
                 bool join = false;
-                if (p1 | p2) {
-                    h = p1 ? kBucketSlots * b1 + (uint32_t)__builtin_ctz(p1)
-                           : kBucketSlots * b2 + (uint32_t)__builtin_ctz(p2);
-                    join = true;
+                if (e1 | e2) {
+                    h = __builtin_popcount(e1) >= __builtin_popcount(e2) ? kBucketSlots * b1 + pick_free(e1, x)
+                                                                         : kBucketSlots * b2 + pick_free(e2, x);
                 } else {
-                    const uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2);
-                    if (e1 | e2) {
-                        h = __builtin_popcount(e1) >= __builtin_popcount(e2) ? kBucketSlots * b1 + pick_free(e1, x)
-                                                                             : kBucketSlots * b2 + pick_free(e2, x);
-                    } else {
-                        // both buckets full: the value's claim, or a free slot, in the stash
-                        uint32_t fe = kNone;
-                        for (uint32_t i = 0; i < kStash / 2; ++i) {
-                            const uint4 e = stash4[i];
-                            if (e.x == x && (e.y & kTagPend)) {
-                                h = T + 2 * i;
-                                join = true;
-                            }
-                            if (e.z == x && (e.w & kTagPend)) {
-                                h = T + 2 * i + 1;
-                                join = true;
-                            }
-                            if (fe == kNone && e.y == kTagEmpty) fe = T + 2 * i;
-                            if (fe == kNone && e.w == kTagEmpty) fe = T + 2 * i + 1;
+                    // both buckets full: the value's claim, or a free slot, in the stash
+                    uint32_t fe = kNone;
+                    for (uint32_t i = 0; i < kStash / 2; ++i) {
+                        const uint4 e = stash4[i];
+                        if (e.x == x && (e.y & kTagPend)) {
+                            h = T + 2 * i;
+                            join = true;
                         }
-                        if (!join) h = fe;
+                        if (e.z == x && (e.w & kTagPend)) {
+                            h = T + 2 * i + 1;
+                            join = true;
+                        }
+                        if (fe == kNone && e.y == kTagEmpty) fe = T + 2 * i;
+                        if (fe == kNone && e.w == kTagEmpty) fe = T + 2 * i + 1;
                     }
+                    if (!join) h = fe;
                 }
                 if (h == kNone) {  // no free slot anywhere
                     bad = true;
                     break;
                 }
+                if (!join) {
+                    const uint64_t old =
+                        atomicCAS((unsigned long long*)&table[h], 0ull, (unsigned long long)mine);
+                    if (old == 0ull) {
+                        hp = h;
+                        break;
+                    }
+                    join = (uint32_t)old == x && ((uint32_t)(old >> 32) & kTagPend);
+                    if (!join && h < T) {  // taken by another value
+                        const uint32_t bit = 1u << (h % kBucketSlots);
+                        if (h / kBucketSlots == b1) e1 &= ~bit; else e2 &= ~bit;
+                    }
+                }
                 if (join) {
                     atomicMin(((uint32_t*)&table[h]) + 1, kTagPend | lane);
-                    hp = h;
-                    break;
-                }
-                if (atomicCAS((unsigned long long*)&table[h], 0ull, (unsigned long long)mine) == 0ull) {
                     hp = h;
                     break;
                 }

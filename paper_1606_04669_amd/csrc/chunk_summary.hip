@@ -150,6 +150,14 @@ __device__ __forceinline__ uint32_t tag_at(const Bucket& B, uint32_t i) {
 // Sorting the minimum level by item id
 // ---------------------------------------------------------------------------
 
+// The item id of counter s: the key of its table entry.
+template <typename IT>
+struct CounterIds {
+    const uint64_t* table;
+    const IT* hpos;
+    __device__ __forceinline__ uint32_t operator()(uint32_t s) const { return (uint32_t)table[hpos[s]]; }
+};
+
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, uint32_t lx) {
     uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, (int)lx);
     uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), (int)lx);
@@ -194,8 +202,8 @@ __device__ __forceinline__ void reg_bitonic_sort(uint64_t (&v)[P], uint32_t lane
 }
 
 // list[0, len) holds counter indices; reorder them by item id.
-template <int P>
-__device__ void sort_level_regs(uint16_t* list, const uint32_t* item, uint32_t len, uint32_t lane) {
+template <int P, typename ID>
+__device__ void sort_level_regs(uint16_t* list, const ID& ids, uint32_t len, uint32_t lane) {
     uint64_t v[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
@@ -203,7 +211,7 @@ __device__ void sort_level_regs(uint16_t* list, const uint32_t* item, uint32_t l
         v[j] = ~0ull;
         if (g < len) {
             const uint32_t s = list[g];
-            v[j] = ((uint64_t)item[s] << 32) | s;
+            v[j] = ((uint64_t)ids(s) << 32) | s;
         }
     }
     reg_bitonic_sort<P>(v, lane);
@@ -215,15 +223,15 @@ __device__ void sort_level_regs(uint16_t* list, const uint32_t* item, uint32_t l
     }
 }
 
-template <int P>
-__device__ void sort_level_dispatch(uint16_t* list, const uint32_t* item, uint32_t len, uint32_t per_lane,
+template <int P, typename ID>
+__device__ void sort_level_dispatch(uint16_t* list, const ID& ids, uint32_t len, uint32_t per_lane,
                                     uint32_t lane) {
     if constexpr (P >= 2) {
         if (per_lane == (uint32_t)P) {
-            sort_level_regs<P>(list, item, len, lane);
+            sort_level_regs<P>(list, ids, len, lane);
             return;
         }
-        if constexpr (P > 2) sort_level_dispatch<P / 2>(list, item, len, per_lane, lane);
+        if constexpr (P > 2) sort_level_dispatch<P / 2>(list, ids, len, per_lane, lane);
     }
 }
 
@@ -251,8 +259,8 @@ constexpr uint32_t kMaxBucket = 48;
 // level's ids differ, so bucket order is id order), then every entry's rank
 // inside its bucket.  Returns false, leaving list untouched, when a bucket is
 // larger than kMaxBucket.
-template <int P>
-__device__ bool sort_level_buckets(uint16_t* list, const uint32_t* item, uint32_t* tkey, uint32_t* hist,
+template <int P, typename ID>
+__device__ bool sort_level_buckets(uint16_t* list, const ID& ids, uint32_t* tkey, uint32_t* hist,
                                    uint32_t len, uint32_t lane) {
     uint32_t sd[P], id[P], pin[P];
     uint32_t orv = 0u, andv = 0xFFFFFFFFu;
@@ -261,7 +269,7 @@ __device__ bool sort_level_buckets(uint16_t* list, const uint32_t* item, uint32_
     for (int j = 0; j < P; ++j) {
         const uint32_t g = lane * P + j;
         const uint32_t s = list[g < len ? g : 0u];
-        id[j] = item[s];
+        id[j] = ids(s);
         sd[j] = s;
         if (g < len) {
             orv |= id[j];
@@ -330,25 +338,25 @@ __device__ bool sort_level_buckets(uint16_t* list, const uint32_t* item, uint32_
     return true;
 }
 
-template <int P>
-__device__ bool sort_level_buckets_dispatch(uint16_t* list, const uint32_t* item, uint32_t* tkey, uint32_t* hist,
+template <int P, typename ID>
+__device__ bool sort_level_buckets_dispatch(uint16_t* list, const ID& ids, uint32_t* tkey, uint32_t* hist,
                                             uint32_t len, uint32_t per_lane, uint32_t lane) {
     if constexpr (P >= 2 && P <= 32) {
-        if (per_lane == (uint32_t)P) return sort_level_buckets<P>(list, item, tkey, hist, len, lane);
+        if (per_lane == (uint32_t)P) return sort_level_buckets<P>(list, ids, tkey, hist, len, lane);
     }
-    if constexpr (P > 2) return sort_level_buckets_dispatch<P / 2>(list, item, tkey, hist, len, per_lane, lane);
+    if constexpr (P > 2) return sort_level_buckets_dispatch<P / 2>(list, ids, tkey, hist, len, per_lane, lane);
     return false;
 }
 
 // Rank sort of list[0, len) by item id, len <= 64: one entry per lane, its
 // rank is the number of smaller ids.
-template <typename IT>
-__device__ void sort_level_rank(IT* list, const uint32_t* item, uint32_t len, uint32_t lane) {
+template <typename IT, typename ID>
+__device__ void sort_level_rank(IT* list, const ID& ids, uint32_t len, uint32_t lane) {
     uint32_t s = 0;
     uint32_t key = 0xFFFFFFFFu;
     if (lane < len) {
         s = list[lane];
-        key = item[s];
+        key = ids(s);
     }
     uint32_t rank = 0;
     for (uint32_t i = 0; i < len; ++i) {
@@ -363,10 +371,10 @@ __device__ void sort_level_rank(IT* list, const uint32_t* item, uint32_t len, ui
 // 8-bit passes), for levels of any size.  Within each group of 64 entries the
 // lanes holding the same digit are found with eight ballots, so equal digits
 // keep their order.  list2, tkey and tkey2 hold len entries each.
-template <typename IT>
-__device__ void sort_level_radix(IT* list, IT* list2, const uint32_t* item, uint32_t* tkey, uint32_t* tkey2,
+template <typename IT, typename ID>
+__device__ void sort_level_radix(IT* list, IT* list2, const ID& ids, uint32_t* tkey, uint32_t* tkey2,
                                  uint32_t* hist, uint32_t len, uint32_t lane) {
-    for (uint32_t g = lane; g < len; g += kWave) tkey[g] = item[list[g]];
+    for (uint32_t g = lane; g < len; g += kWave) tkey[g] = ids(list[g]);
     wave_sync();
     IT* src = list;
     IT* dst = list2;
@@ -423,16 +431,16 @@ __device__ void sort_level_radix(IT* list, IT* list2, const uint32_t* item, uint
     }
 }
 
-template <int P>
-__device__ void sort_level(uint16_t* list, const uint32_t* item, uint32_t* tkey, uint32_t* hist, uint32_t len,
+template <int P, typename ID>
+__device__ void sort_level(uint16_t* list, const ID& ids, uint32_t* tkey, uint32_t* hist, uint32_t len,
                            uint32_t lane) {
     if (len <= 64) {
-        sort_level_rank<uint16_t>(list, item, len, lane);
+        sort_level_rank<uint16_t>(list, ids, len, lane);
     } else {
         const uint32_t per_lane = next_pow2((len + 63) / 64);
-        if (!sort_level_buckets_dispatch<P>(list, item, tkey, hist, len, per_lane, lane)) {
+        if (!sort_level_buckets_dispatch<P>(list, ids, tkey, hist, len, per_lane, lane)) {
             wave_sync();
-            sort_level_dispatch<P>(list, item, len, per_lane, lane);
+            sort_level_dispatch<P>(list, ids, len, per_lane, lane);
         }
     }
     wave_sync();
@@ -500,10 +508,10 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
     uint64_t* table = (uint64_t*)(sb + L.off_table);
     const uint4* tbl4 = (const uint4*)(sb + L.off_table);
     uint32_t* cnt = (uint32_t*)(sb + L.off_cnt);
-    uint32_t* item = o_item;  // ids and errors live in the output arrays
-    uint32_t* err = o_err;
+    uint32_t* err = o_err;  // errors live in the output array; ids are the table keys
     idx_t* hpos = (idx_t*)(sb + L.off_hpos);
     idx_t* list = (idx_t*)(sb + L.off_list);
+    const CounterIds<idx_t> ids{table, hpos};
     uint8_t* mark = (uint8_t*)(sb + L.off_mark);
     uint32_t* tkey = (uint32_t*)(sb + L.off_tkey);
     idx_t* list2 = (idx_t*)(sb + L.off_list2);
@@ -789,12 +797,12 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                     const unsigned long long tsrt = KSTAT_NOW();
                     if constexpr (G) {
                         if (len <= 64)
-                            sort_level_rank<idx_t>(list, item, len, lane);
+                            sort_level_rank<idx_t>(list, ids, len, lane);
                         else
-                            sort_level_radix<idx_t>(list, list2, item, tkey, tkey2, hist, len, lane);
+                            sort_level_radix<idx_t>(list, list2, ids, tkey, tkey2, hist, len, lane);
                         wave_sync();
                     } else {
-                        sort_level<P>(list, item, tkey, hist, len, lane);
+                        sort_level<P>(list, ids, tkey, hist, len, lane);
                         // the histogram overlaid the victim marks: zero them again
                         for (uint32_t i = 4 * lane; i < kHistBytes; i += 4 * kWave) *(uint32_t*)(mark + i) = 0u;
                         wave_sync();
@@ -856,7 +864,6 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                     cnt[myslot] = m + 1u;
                     err[myslot] = m;
                 }
-                item[myslot] = x;
                 hpos[myslot] = (idx_t)hp;
                 table[hp] = make_entry(x, myslot + 1u);
             } else {
@@ -912,7 +919,10 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         for (uint32_t s = lane; s < k; s += kWave) mn = min(mn, cnt[s]);
         mo = wave_min_u32(mn);
     }
-    for (uint32_t s = lane; s < size; s += kWave) o_cnt[s] = cnt[s];  // ids and errors are in place
+    for (uint32_t s = lane; s < size; s += kWave) {  // errors are already in place
+        o_item[s] = ids(s);
+        o_cnt[s] = cnt[s];
+    }
     if (lane == 0) {
         *o_size = size;
         *o_min = mo;

@@ -2,9 +2,10 @@
 // chunk_summary kernel.  One wave owns one layout.  The per-block state (hash
 // table, counts, minimum-level list) lives in LDS when it fits, otherwise in
 // a global-memory slab of state_bytes per block; the input ring and a few
-// small per-window arrays always live in LDS.  Item ids and errors are
-// written straight to the block's output arrays in device memory (they are
-// read only when a level is sorted), which keeps them out of LDS.
+// small per-window arrays always live in LDS.  A counter's item id is the
+// key of its hash-table entry, and errors are written straight to the
+// block's output array in device memory (read only at the end), which keeps
+// both out of LDS.
 #pragma once
 
 #include <stdint.h>

@@ -447,6 +447,74 @@ __device__ void sort_level(uint16_t* list, const ID& ids, uint32_t* tkey, uint32
 }
 
 // ---------------------------------------------------------------------------
+// Listing a new minimum level (LDS-resident state), out of line
+// ---------------------------------------------------------------------------
+
+extern __shared__ __align__(16) unsigned char smem[];
+
+// Finds the minimum count m of the k counters and lists the counters at m in
+// id order; state at LDS byte offset sbo.  `prev` is the level just
+// exhausted: one pass finds the minimum and collects the counters at
+// prev + 1, the usual next level, and a second pass collects the true
+// minimum level when it differs.  Returns m << 32 | length.  Kept out of line:
+// it runs once per level, and inlined its registers crowd the window loop.
+template <int P>
+__device__ __attribute__((noinline)) uint64_t build_level_lds(uint32_t sbo, ChunkLayout L, uint32_t prev,
+                                                             uint32_t lane) {
+    const uint32_t k = L.k;
+    const uint32_t* cnt = (const uint32_t*)(smem + sbo + L.off_cnt);
+    uint16_t* list = (uint16_t*)(smem + sbo + L.off_list);
+    uint8_t* mark = (uint8_t*)(smem + sbo + L.off_mark);
+    uint32_t* tkey = (uint32_t*)(smem + sbo + L.off_tkey);
+    uint32_t* hist = (uint32_t*)(smem + sbo + L.off_hist);
+    const CounterIds<uint16_t> ids{(const uint64_t*)(smem + sbo + L.off_table),
+                                   (const uint16_t*)(smem + sbo + L.off_hpos)};
+    const uint32_t guess = prev + 1u;
+    uint32_t mn = 0xFFFFFFFFu, len = 0;
+    for (uint32_t b = 0; b < k; b += 4 * kWave) {
+        uint32_t cv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t s = b + j * kWave + lane;
+            cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            mn = min(mn, cv[j]);
+            const bool take = cv[j] == guess;
+            const uint64_t bm = ballot(take);
+            if (take) list[len + mbcnt(bm)] = (uint16_t)(b + j * kWave + lane);
+            len = uniform(len + popc64(bm));
+        }
+    }
+    const uint32_t m = uniform(wave_min_u32(mn));
+    if (m != guess) {
+        len = 0;
+        for (uint32_t b = 0; b < k; b += 4 * kWave) {
+            uint32_t cv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t s = b + j * kWave + lane;
+                cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool take = cv[j] == m;
+                const uint64_t bm = ballot(take);
+                if (take) list[len + mbcnt(bm)] = (uint16_t)(b + j * kWave + lane);
+                len = uniform(len + popc64(bm));
+            }
+        }
+    }
+    wave_sync();
+    sort_level<P>(list, ids, tkey, hist, len, lane);
+    // the histogram overlaid the victim marks: zero them again
+    for (uint32_t i = 4 * lane; i < kHistBytes; i += 4 * kWave) *(uint32_t*)(mark + i) = 0u;
+    wave_sync();
+    return ((uint64_t)m << 32) | len;
+}
+
+// ---------------------------------------------------------------------------
 // Input staging
 // ---------------------------------------------------------------------------
 
@@ -752,30 +820,14 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                     // level exhausted: list the new minimum level, by id
                     const unsigned long long tl = KSTAT_NOW();
                     KSTAT_ADD(5, 1);
-                    // one pass finds the minimum and collects the counters at
-                    // m + 1, the usual next level; a second pass collects the
-                    // true minimum level when it differs
-                    const uint32_t guess = m + 1u;
-                    uint32_t mn = 0xFFFFFFFFu, len = 0;
-                    for (uint32_t b = 0; b < k; b += 4 * kWave) {
-                        uint32_t cv[4];
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const uint32_t s = b + j * kWave + lane;
-                            cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
-                        }
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            mn = min(mn, cv[j]);
-                            const bool take = cv[j] == guess;
-                            const uint64_t bm = ballot(take);
-                            if (take) list[len + mbcnt(bm)] = (idx_t)(b + j * kWave + lane);
-                            len = uniform(len + popc64(bm));
-                        }
-                    }
-                    m = uniform(wave_min_u32(mn));
-                    if (m != guess) {
-                        len = 0;
+                    uint32_t len = 0;
+                    const unsigned long long tsrt = KSTAT_NOW();
+                    if constexpr (G) {
+                        // one pass finds the minimum and collects the counters at
+                        // m + 1, the usual next level; a second pass collects the
+                        // true minimum level when it differs
+                        const uint32_t guess = m + 1u;
+                        uint32_t mn = 0xFFFFFFFFu;
                         for (uint32_t b = 0; b < k; b += 4 * kWave) {
                             uint32_t cv[4];
 #pragma unroll
@@ -785,27 +837,43 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                             }
 #pragma unroll
                             for (int j = 0; j < 4; ++j) {
-                                const bool take = cv[j] == m;
+                                mn = min(mn, cv[j]);
+                                const bool take = cv[j] == guess;
                                 const uint64_t bm = ballot(take);
                                 if (take) list[len + mbcnt(bm)] = (idx_t)(b + j * kWave + lane);
                                 len = uniform(len + popc64(bm));
                             }
                         }
-                    }
-                    wave_sync();
-                    KSTAT_ADD(7, KSTAT_NOW() - tl);
-                    const unsigned long long tsrt = KSTAT_NOW();
-                    if constexpr (G) {
+                        m = uniform(wave_min_u32(mn));
+                        if (m != guess) {
+                            len = 0;
+                            for (uint32_t b = 0; b < k; b += 4 * kWave) {
+                                uint32_t cv[4];
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) {
+                                    const uint32_t s = b + j * kWave + lane;
+                                    cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
+                                }
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) {
+                                    const bool take = cv[j] == m;
+                                    const uint64_t bm = ballot(take);
+                                    if (take) list[len + mbcnt(bm)] = (idx_t)(b + j * kWave + lane);
+                                    len = uniform(len + popc64(bm));
+                                }
+                            }
+                        }
+                        wave_sync();
+
                         if (len <= 64)
                             sort_level_rank<idx_t>(list, ids, len, lane);
                         else
                             sort_level_radix<idx_t>(list, list2, ids, tkey, tkey2, hist, len, lane);
                         wave_sync();
                     } else {
-                        sort_level<P>(list, ids, tkey, hist, len, lane);
-                        // the histogram overlaid the victim marks: zero them again
-                        for (uint32_t i = 4 * lane; i < kHistBytes; i += 4 * kWave) *(uint32_t*)(mark + i) = 0u;
-                        wave_sync();
+                        const uint64_t r = build_level_lds<P>((uint32_t)(sb - smem), L, m, lane);
+                        m = uniform((uint32_t)(r >> 32));
+                        len = uniform((uint32_t)r);
                     }
                     list_len = len;
                     list_ptr = 0;

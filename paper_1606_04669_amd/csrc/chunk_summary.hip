@@ -514,6 +514,65 @@ __device__ __attribute__((noinline)) uint64_t build_level_lds(uint32_t sbo, Chun
     return ((uint64_t)m << 32) | len;
 }
 
+// The same for state in device memory (slab sb, 32-bit indices; the sort
+// histogram in LDS at lds + off_hist): levels of at most 64 entries by rank,
+// larger ones by the stable radix sort.
+__device__ __attribute__((noinline)) uint64_t build_level_global(unsigned char* sb, unsigned char* lds,
+                                                                 ChunkLayout L, uint32_t prev, uint32_t lane) {
+    const uint32_t k = L.k;
+    const uint32_t* cnt = (const uint32_t*)(sb + L.off_cnt);
+    uint32_t* list = (uint32_t*)(sb + L.off_list);
+    uint32_t* list2 = (uint32_t*)(sb + L.off_list2);
+    uint32_t* tkey = (uint32_t*)(sb + L.off_tkey);
+    uint32_t* tkey2 = (uint32_t*)(sb + L.off_tkey2);
+    uint32_t* hist = (uint32_t*)(lds + L.off_hist);
+    const CounterIds<uint32_t> ids{(const uint64_t*)(sb + L.off_table), (const uint32_t*)(sb + L.off_hpos)};
+    const uint32_t guess = prev + 1u;
+    uint32_t mn = 0xFFFFFFFFu, len = 0;
+    for (uint32_t b = 0; b < k; b += 4 * kWave) {
+        uint32_t cv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t s = b + j * kWave + lane;
+            cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            mn = min(mn, cv[j]);
+            const bool take = cv[j] == guess;
+            const uint64_t bm = ballot(take);
+            if (take) list[len + mbcnt(bm)] = b + j * kWave + lane;
+            len = uniform(len + popc64(bm));
+        }
+    }
+    const uint32_t m = uniform(wave_min_u32(mn));
+    if (m != guess) {
+        len = 0;
+        for (uint32_t b = 0; b < k; b += 4 * kWave) {
+            uint32_t cv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t s = b + j * kWave + lane;
+                cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool take = cv[j] == m;
+                const uint64_t bm = ballot(take);
+                if (take) list[len + mbcnt(bm)] = b + j * kWave + lane;
+                len = uniform(len + popc64(bm));
+            }
+        }
+    }
+    wave_sync();
+    if (len <= 64)
+        sort_level_rank<uint32_t>(list, ids, len, lane);
+    else
+        sort_level_radix<uint32_t>(list, list2, ids, tkey, tkey2, hist, len, lane);
+    wave_sync();
+    return ((uint64_t)m << 32) | len;
+}
+
 // ---------------------------------------------------------------------------
 // Input staging
 // ---------------------------------------------------------------------------
@@ -823,53 +882,9 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                     uint32_t len = 0;
                     const unsigned long long tsrt = KSTAT_NOW();
                     if constexpr (G) {
-                        // one pass finds the minimum and collects the counters at
-                        // m + 1, the usual next level; a second pass collects the
-                        // true minimum level when it differs
-                        const uint32_t guess = m + 1u;
-                        uint32_t mn = 0xFFFFFFFFu;
-                        for (uint32_t b = 0; b < k; b += 4 * kWave) {
-                            uint32_t cv[4];
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) {
-                                const uint32_t s = b + j * kWave + lane;
-                                cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
-                            }
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) {
-                                mn = min(mn, cv[j]);
-                                const bool take = cv[j] == guess;
-                                const uint64_t bm = ballot(take);
-                                if (take) list[len + mbcnt(bm)] = (idx_t)(b + j * kWave + lane);
-                                len = uniform(len + popc64(bm));
-                            }
-                        }
-                        m = uniform(wave_min_u32(mn));
-                        if (m != guess) {
-                            len = 0;
-                            for (uint32_t b = 0; b < k; b += 4 * kWave) {
-                                uint32_t cv[4];
-#pragma unroll
-                                for (int j = 0; j < 4; ++j) {
-                                    const uint32_t s = b + j * kWave + lane;
-                                    cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
-                                }
-#pragma unroll
-                                for (int j = 0; j < 4; ++j) {
-                                    const bool take = cv[j] == m;
-                                    const uint64_t bm = ballot(take);
-                                    if (take) list[len + mbcnt(bm)] = (idx_t)(b + j * kWave + lane);
-                                    len = uniform(len + popc64(bm));
-                                }
-                            }
-                        }
-                        wave_sync();
-
-                        if (len <= 64)
-                            sort_level_rank<idx_t>(list, ids, len, lane);
-                        else
-                            sort_level_radix<idx_t>(list, list2, ids, tkey, tkey2, hist, len, lane);
-                        wave_sync();
+                        const uint64_t r = build_level_global(sb, lds, L, m, lane);
+                        m = uniform((uint32_t)(r >> 32));
+                        len = uniform((uint32_t)r);
                     } else {
                         const uint64_t r = build_level_lds<P>((uint32_t)(sb - smem), L, m, lane);
                         m = uniform((uint32_t)(r >> 32));

@@ -456,11 +456,10 @@ extern __shared__ __align__(16) unsigned char smem[];
 // id order; state at LDS byte offset sbo.  `prev` is the level just
 // exhausted: one pass finds the minimum and collects the counters at
 // prev + 1, the usual next level, and a second pass collects the true
-// minimum level when it differs.  Returns m << 32 | length.  Kept out of line:
-// it runs once per level, and inlined its registers crowd the window loop.
+// minimum level when it differs.  Returns m << 32 | length.
 template <int P>
-__device__ __attribute__((noinline)) uint64_t build_level_lds(uint32_t sbo, ChunkLayout L, uint32_t prev,
-                                                             uint32_t lane) {
+__device__ __forceinline__ uint64_t level_lds_body(uint32_t sbo, const ChunkLayout& L, uint32_t prev,
+                                                   uint32_t lane) {
     const uint32_t k = L.k;
     const uint32_t* cnt = (const uint32_t*)(smem + sbo + L.off_cnt);
     uint16_t* list = (uint16_t*)(smem + sbo + L.off_list);
@@ -514,11 +513,22 @@ __device__ __attribute__((noinline)) uint64_t build_level_lds(uint32_t sbo, Chun
     return ((uint64_t)m << 32) | len;
 }
 
+// The same kept out of line, for the large register classes: it runs once
+// per level, and inlined its sort registers crowd the window loop into
+// scalar-register spills.  (The call saves registers to scratch memory, so
+// the small classes, which gain nothing from it, keep it inline.)
+template <int P>
+__device__ __attribute__((noinline)) uint64_t build_level_lds(uint32_t sbo, ChunkLayout L, uint32_t prev,
+                                                             uint32_t lane) {
+    return level_lds_body<P>(sbo, L, prev, lane);
+}
+
 // The same for state in device memory (slab sb, 32-bit indices; the sort
 // histogram in LDS at lds + off_hist): levels of at most 64 entries by rank,
-// larger ones by the stable radix sort.
-__device__ __attribute__((noinline)) uint64_t build_level_global(unsigned char* sb, unsigned char* lds,
-                                                                 ChunkLayout L, uint32_t prev, uint32_t lane) {
+// larger ones by the stable radix sort.  Inline: out of line it saved nothing
+// here (this path waits on device memory, not on instruction issue).
+__device__ __forceinline__ uint64_t build_level_global(unsigned char* sb, unsigned char* lds,
+                                                       const ChunkLayout& L, uint32_t prev, uint32_t lane) {
     const uint32_t k = L.k;
     const uint32_t* cnt = (const uint32_t*)(sb + L.off_cnt);
     uint32_t* list = (uint32_t*)(sb + L.off_list);
@@ -886,7 +896,11 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                         m = uniform((uint32_t)(r >> 32));
                         len = uniform((uint32_t)r);
                     } else {
-                        const uint64_t r = build_level_lds<P>((uint32_t)(sb - smem), L, m, lane);
+                        uint64_t r;
+                        if constexpr (P >= 16)
+                            r = build_level_lds<P>((uint32_t)(sb - smem), L, m, lane);
+                        else
+                            r = level_lds_body<P>((uint32_t)(sb - smem), L, m, lane);
                         m = uniform((uint32_t)(r >> 32));
                         len = uniform((uint32_t)r);
                     }

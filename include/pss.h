@@ -211,6 +211,8 @@ typedef struct {
     uint32_t slots;        /* launches in flight (0: 2; at most 8) */
     uint32_t max_requests; /* requests per launch (0: 4096) */
     uint64_t block_len;    /* target block length for appends with chunks = 0 (0: 16384) */
+    uint64_t stage_bytes;  /* pinned host staging per slot, allocated at creation; a launch's
+                              items fit it unless one append alone is larger (0: 256 MiB) */
 } pss_server_opts;
 
 typedef struct {

@@ -37,7 +37,7 @@ class BatchInfo(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     """pss_server_opts"""
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_uint32), ("max_requests", ctypes.c_uint32),
-                ("block_len", ctypes.c_uint64)]
+                ("block_len", ctypes.c_uint64), ("stage_bytes", ctypes.c_uint64)]
 
 
 class ServerResult(ctypes.Structure):
@@ -394,9 +394,9 @@ class Server:
     referenced here until their ticket is waited for."""
 
     def __init__(self, ctx: Context, ks, hbm_budget: int = 0, slots: int = 0, max_requests: int = 0,
-                 block_len: int = 0):
+                 block_len: int = 0, stage_bytes: int = 0):
         a_k = np.ascontiguousarray(np.asarray(ks, dtype=np.uint32))
-        opts = ServerOpts(hbm_budget, slots, max_requests, block_len)
+        opts = ServerOpts(hbm_budget, slots, max_requests, block_len, stage_bytes)
         h = ctypes.c_void_p()
         _check(lib().pss_server_create(ctx.handle, len(a_k), a_k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                        ctypes.byref(opts), ctypes.byref(h)), "pss_server_create")

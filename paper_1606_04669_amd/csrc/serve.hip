@@ -176,7 +176,7 @@ void stage_items(const Slot& sl, char* hp, const std::vector<uint64_t>& item_off
     }
     const size_t kParallelBytes = 16u << 20;
     unsigned nt = std::thread::hardware_concurrency();
-    nt = std::max(1u, std::min(nt, 8u));
+    nt = std::max(1u, std::min(nt, 16u));
     if (total_bytes < kParallelBytes || nt == 1) {
         for (const Piece& p : pieces) memcpy(p.dst, p.src, p.bytes);
         return;
@@ -492,19 +492,23 @@ void server_loop(pss_server* srv) {
             Slot& sl = srv->slots[free_slot];
             const uint64_t seq = ++srv->launches;
             std::unordered_set<uint32_t> blocked;
-            size_t used = 0;
+            size_t used = 0, staged = 0;
             std::deque<Request*> rest;
             std::vector<int> wait_slots;
             while (!srv->pending.empty() && sl.reqs.size() < srv->opts.max_requests && rest.size() < kScanLimit) {
                 Request* q = srv->pending.front();
                 srv->pending.pop_front();
                 size_t need = q->type == kAppend ? append_bytes(q->n, srv->ks[q->sid], q->chunks) : query_bytes(q->cap);
-                if (blocked.count(q->sid) || (used + need > srv->slot_budget && !sl.reqs.empty())) {
+                const size_t qitems = q->type == kAppend ? q->n * 4 : 0;
+                if (blocked.count(q->sid) ||
+                    (!sl.reqs.empty() && (used + need > srv->slot_budget ||
+                                          staged + qitems > (size_t)srv->opts.stage_bytes))) {
                     blocked.insert(q->sid);  // later requests on it keep their order
                     rest.push_back(q);
                     continue;
                 }
                 used += need;
+                staged += qitems;
                 blocked.insert(q->sid);  // at most one request per summary per launch
                 q->launch = (uint32_t)seq;
                 q->t_launch = Clock::now();
@@ -606,6 +610,7 @@ int pss_server_create(pss_ctx* ctx, uint32_t nsummaries, const uint32_t* h_ks, c
         srv->opts.slots = opts && opts->slots ? std::min<uint32_t>(opts->slots, 8) : 2;
         srv->opts.max_requests = opts && opts->max_requests ? opts->max_requests : 4096;
         srv->opts.block_len = opts && opts->block_len ? opts->block_len : (1ull << 14);
+        srv->opts.stage_bytes = opts && opts->stage_bytes ? opts->stage_bytes : (256ull << 20);
         srv->slot_budget = (size_t)(srv->opts.hbm_budget / srv->opts.slots);
         srv->nsum = nsummaries;
         srv->ks.assign(h_ks, h_ks + nsummaries);
@@ -643,6 +648,14 @@ int pss_server_create(pss_ctx* ctx, uint32_t nsummaries, const uint32_t* h_ks, c
                 hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
                 hipEventCreate(&sl.t0) != hipSuccess || hipEventCreate(&sl.t1) != hipSuccess)
                 rc = PSS_EDEVICE;
+        }
+        // staging for a launch's items, allocated up front: pinned host memory
+        // and device memory for the items plus their block summaries
+        for (Slot& sl : srv->slots) {
+            if (rc != PSS_OK) break;
+            rc = grow_pinned(&sl.pin, &sl.pin_bytes, (size_t)srv->opts.stage_bytes);
+            if (rc == PSS_OK)
+                rc = sl.dev.grow(std::min<size_t>(srv->slot_budget, 2 * (size_t)srv->opts.stage_bytes));
         }
         if (rc == PSS_OK) srv->worker = std::thread(server_loop, srv);
     } catch (...) {

@@ -22,6 +22,12 @@ namespace {
 // Device memory the HBM-resident block states of one update may take; the
 // planner lowers C below this.
 constexpr size_t kStateBudget = 16ull << 30;
+// Rounds of resident waves the planner aims for: more blocks even out the
+// tail of the block launch, fewer keep the reduction tree small.
+#ifndef PSS_PLAN_ROUNDS
+#define PSS_PLAN_ROUNDS 4
+#endif
+constexpr uint64_t kPlanRounds = PSS_PLAN_ROUNDS;
 // Concurrent COMBINE workgroups (one scratch slab each) when a COMBINE's
 // arrays do not fit LDS.
 constexpr uint32_t kCombineSlabsPerCu = 2;
@@ -282,7 +288,8 @@ uint32_t pss_plan_chunks(const pss_ctx* ctx, uint64_t n, uint32_t k) {
     const ChunkLayout L = chunk_layout(k, ctx->lds_max);
     uint64_t per_cu = ctx->lds_per_cu / std::max<uint32_t>(1, L.lds_bytes);
     per_cu = std::min<uint64_t>(std::max<uint64_t>(per_cu, 1), 32);  // 32 waves per CU at most
-    uint64_t want = (uint64_t)ctx->cu_count * per_cu * 4;
+    // many resident waves (small k): twice the rounds, the tree stays cheap
+    uint64_t want = (uint64_t)ctx->cu_count * per_cu * (per_cu >= 8 ? 2 * kPlanRounds : kPlanRounds);
     uint64_t cap_len = n / (16ull * k);
     if (cap_len < 1) cap_len = 1;
     uint64_t c = std::min(want, cap_len);

@@ -104,7 +104,7 @@ int pss_create(pss_ctx* ctx, uint32_t k, pss_summary** out);
  * accepted. */
 void pss_destroy(pss_summary* s);
 
-/* Append n items (device array d_items, n < 2^32) to summary s:
+/* Append n items (device array d_items, n < 2^32 - 64) to summary s:
  *   B = fixed-tree COMBINE of the Space Saving summaries of C blocks of
  *       d_items (Algorithm 1 up to the reduction), then S <- COMBINE(S, B)
  *       and N <- N + n.
@@ -147,7 +147,7 @@ int pss_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint3
  * Stream s is the device array h_items[s][0, h_lens[s]) with k = h_ks[s]
  * counters; its result is exactly that of pss_run on it with
  * C = h_chunks[s] (Algorithm 1 with Algorithm 2 as the reduction): the batch
- * changes scheduling only.  Requires 2 <= k_s <= n_s, n_s < 2^32 and
+ * changes scheduling only.  Requires 2 <= k_s <= n_s, n_s < 2^32 - 64 and
  * k_s <= pss_batch_max_k() (PSS_ERANGE otherwise). */
 typedef struct pss_batch pss_batch;
 
@@ -247,7 +247,7 @@ void pss_server_destroy(pss_server* srv);
 /* Submit an append of h_items[0, n) (host memory, caller-owned, valid until
  * the ticket completes) to summary sid with C = chunks blocks (0: chosen from
  * opts.block_len, reported by pss_server_wait).  Returns at once with
- * *ticket.  PSS_ERANGE if n >= 2^32 or the append can never fit the budget. */
+ * *ticket.  PSS_ERANGE if n >= 2^32 - 64 or the append can never fit the budget. */
 int pss_server_append(pss_server* srv, uint32_t sid, const uint32_t* h_items, uint64_t n, uint32_t chunks,
                       uint64_t* ticket);
 
@@ -276,6 +276,15 @@ int pss_phase_times(pss_ctx* ctx, double* ms, uint32_t* launches, int reset);
 
 /* Static description of an error code. */
 const char* pss_strerror(int code);
+
+/* Diagnostics for PSS_EDEVICE: the hipError_t of the last failed kernel
+ * launch (or launch-side runtime call) that a call made on this host thread
+ * turned into PSS_EDEVICE (0 if none; invariant failures that a kernel
+ * reports in its output are not recorded), and the HIP name of a hipError_t
+ * value (a static string).  The server's own launches run on its thread and
+ * report PSS_EDEVICE through their requests. */
+int pss_last_device_error(void);
+const char* pss_device_error_name(int hip_error);
 
 #ifdef __cplusplus
 }

@@ -80,6 +80,10 @@ def lib():
         u32p, u64p = ctypes.POINTER(u32), ctypes.POINTER(u64)
         L.pss_strerror.restype = ctypes.c_char_p
         L.pss_strerror.argtypes = [i32]
+        L.pss_last_device_error.restype = i32
+        L.pss_last_device_error.argtypes = []
+        L.pss_device_error_name.restype = ctypes.c_char_p
+        L.pss_device_error_name.argtypes = [i32]
         L.pss_ctx_create.argtypes = [i32, ctypes.POINTER(vp)]
         L.pss_ctx_destroy.argtypes = [vp]
         L.pss_ctx_destroy.restype = None
@@ -129,8 +133,18 @@ def strerror(code: int) -> str:
     return lib().pss_strerror(code).decode()
 
 
+def last_device_error() -> tuple[int, str]:
+    """The HIP error behind this thread's last PSS_EDEVICE from a launch."""
+    e = lib().pss_last_device_error()
+    return e, lib().pss_device_error_name(e).decode()
+
+
 def _check(rc: int, what: str, required: int | None = None):
     if rc != PSS_OK:
+        if rc == PSS_EDEVICE:
+            e, name = last_device_error()
+            if e:
+                what = "%s [%s]" % (what, name)
         raise PssError(rc, what, required)
 
 

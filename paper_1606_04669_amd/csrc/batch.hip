@@ -96,6 +96,7 @@ struct pss_batch {
     uint32_t* d_queues = nullptr;
     DevEntry* d_out = nullptr;
     uint32_t* d_counts = nullptr;
+    uint32_t* d_errs = nullptr;  // error scratch of the blocks
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
 
@@ -148,6 +149,7 @@ int build_plan(pss_batch* b, const std::vector<uint32_t>& sel, const Tuning& t, 
             h.d.begin = (uint64_t)c * n / C;  // Algorithm 1's block bounds
             h.d.end = (uint64_t)(c + 1) * n / C;
             h.d.out = 0;
+            h.d.eoff = 0;
             h.d.k = k;
             h.d.slots_x16 = t.slots_x16 ? t.slots_x16 : ChunkLayout::default_slots_x16(k);
             h.cls = class_index(class_lanes(k));
@@ -175,10 +177,12 @@ int build_plan(pss_batch* b, const std::vector<uint32_t>& sel, const Tuning& t, 
         }
     }
     std::vector<uint32_t> where(hb.size());
-    uint64_t off = 0;
+    uint64_t off = 0, eoff = 0;
     for (uint32_t i = 0; i < b->nblocks; ++i) {
         hb[i].d.out = off;
         off += hb[i].d.k;
+        hb[i].d.eoff = eoff;
+        eoff += ChunkLayout::make(hb[i].d.k, false, hb[i].d.slots_x16).err_stride;
         where[first_of[hb[i].stream] + hb[i].c] = i;
     }
     b->entries = off;
@@ -259,7 +263,8 @@ int build_plan(pss_batch* b, const std::vector<uint32_t>& sel, const Tuning& t, 
     const size_t qb = 256;
     const size_t ob = align_up(b->out_entries * sizeof(DevEntry), 256);
     const size_t cb = align_up((size_t)b->nstreams * 4, 256);
-    const size_t total = 3 * e4 + 2 * h4 + bb + nb + rb + qb + ob + cb;
+    const size_t eb = align_up(eoff * 4, 256);  // error scratch of the blocks
+    const size_t total = 3 * e4 + 2 * h4 + bb + nb + rb + qb + ob + cb + eb;
     int rc = b->mem.grow(total);
     if (rc != PSS_OK) return rc;
     char* p = (char*)b->mem.ptr;
@@ -273,7 +278,8 @@ int build_plan(pss_batch* b, const std::vector<uint32_t>& sel, const Tuning& t, 
     b->d_reps = (BatchReport*)p; p += rb;
     b->d_queues = (uint32_t*)p; p += qb;
     b->d_out = (DevEntry*)p; p += ob;
-    b->d_counts = (uint32_t*)p;
+    b->d_counts = (uint32_t*)p; p += cb;
+    b->d_errs = (uint32_t*)p;
     std::vector<BatchBlock> db(hb.size());
     for (size_t i = 0; i < hb.size(); ++i) db[i] = hb[i].d;
     if (hipMemcpy(b->d_blocks, db.data(), db.size() * sizeof(BatchBlock), hipMemcpyHostToDevice) != hipSuccess ||
@@ -299,7 +305,7 @@ int enqueue(pss_batch* b, hipStream_t st) {
                                        cl.waves, cl.grid,
                                        BlockSummaries{b->sums.item, b->sums.cnt, b->sums.err, b->sums.size + cl.first,
                                                       b->sums.min + cl.first},
-                                       ss));
+                                       b->d_errs, ss));
         if (rc != PSS_OK) return rc;
         if (hipEventRecord(b->join[i], ss) != hipSuccess || hipStreamWaitEvent(st, b->join[i], 0) != hipSuccess)
             return PSS_EDEVICE;
@@ -453,7 +459,7 @@ int pss_batch_create(pss_ctx* ctx, uint32_t nstreams, const uint32_t* const* h_i
     bool any_auto = false;
     for (uint32_t s = 0; s < nstreams; ++s) {
         if (!h_items[s] || h_ks[s] < 2) return PSS_EINVAL;
-        if ((uint64_t)h_ks[s] > h_lens[s] || h_lens[s] >= (1ull << 32) || h_ks[s] > kcap) return PSS_ERANGE;
+        if ((uint64_t)h_ks[s] > h_lens[s] || h_lens[s] >= kStreamBound || h_ks[s] > kcap) return PSS_ERANGE;
         if (h_chunks[s] > kMaxChunks) return PSS_ERANGE;
         if (h_chunks[s] == 0) any_auto = true;
     }

@@ -58,10 +58,14 @@ __device__ unsigned long long g_kstats[24];
 #define KSTAT_FLUSH()
 #endif
 
-// Table entry: key | tag << 32 with tag 0 = empty, counter index + 1 (below
-// 2^31) = live, kTagPend | lane = claimed by a lane during a window.
+// Table entry: key | tag << 32 with tag 0 = empty, 1 .. kTagVict - 1 = a
+// counter and its count; during a window, kTagVict + j = the counter of
+// count m that the window's j-th new item would evict, kTagPend + lane =
+// claimed by a lane (so a block holds fewer than kTagVict items).
 constexpr uint32_t kTagEmpty = 0u;
-constexpr uint32_t kTagPend = 0x80000000u;
+constexpr uint32_t kTagVict = 0xFFFFFF80u;
+constexpr uint32_t kTagPend = 0xFFFFFFC0u;
+static_assert(kTagVict == kStreamBound, "every count of a block stays below the window tags");
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 // Block summary size written when a loop bound that the algorithm guarantees
 // is exceeded (an internal invariant failed): the host reports a device error
@@ -85,7 +89,7 @@ __device__ __forceinline__ uint32_t alt_bucket(uint32_t x, uint32_t nb, uint32_t
     return b2 != b1 ? b2 : (b1 + 1 == nb ? 0u : b1 + 1);
 }
 
-__device__ __forceinline__ bool live_tag(uint32_t tag) { return tag - 1u < 0x7FFFFFFFu; }
+__device__ __forceinline__ bool live_tag(uint32_t tag) { return tag - 1u < kTagVict - 1u; }
 
 // One bucket: kBucketSlots key/tag pairs, read with kBucketSlots / 2
 // 16-byte loads.
@@ -150,13 +154,18 @@ __device__ __forceinline__ uint32_t tag_at(const Bucket& B, uint32_t i) {
 // Sorting the minimum level by item id
 // ---------------------------------------------------------------------------
 
-// The item id of counter s: the key of its table entry.
-template <typename IT>
-struct CounterIds {
+// The item id of the counter in slot s: the key of its table entry.
+struct SlotIds {
     const uint64_t* table;
-    const IT* hpos;
-    __device__ __forceinline__ uint32_t operator()(uint32_t s) const { return (uint32_t)table[hpos[s]]; }
+    __device__ __forceinline__ uint32_t operator()(uint32_t s) const { return (uint32_t)table[s]; }
 };
+
+// Count of a slot's entry (the high word), or ~0 when the slot holds no
+// counter (empty, or claimed during a window).
+__device__ __forceinline__ uint32_t slot_count(const uint32_t* words, uint32_t s) {
+    const uint32_t c = words[2 * s + 1];
+    return live_tag(c) ? c : 0xFFFFFFFFu;
+}
 
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, uint32_t lx) {
     uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, (int)lx);
@@ -257,9 +266,10 @@ constexpr uint32_t kMaxBucket = 48;
 // Bucketed sort of list[0, len) by item id for len > 64, 64 * P >= len:
 // a counting sort on 8 bits of the id (the top 8 of the bits where the
 // level's ids differ, so bucket order is id order), then every entry's rank
-// inside its bucket.  Returns false, leaving list untouched, when a bucket is
-// larger than kMaxBucket.
-template <int P, typename ID>
+// inside its bucket.  Returns false, with list as it was, when a bucket is
+// larger than kMaxBucket.  OVER: hist lies over list (the list is held in
+// registers from the first read to the final write).
+template <int P, bool OVER, typename ID>
 __device__ bool sort_level_buckets(uint16_t* list, const ID& ids, uint32_t* tkey, uint32_t* hist,
                                    uint32_t len, uint32_t lane) {
     uint32_t sd[P], id[P], pin[P];
@@ -292,7 +302,18 @@ __device__ bool sort_level_buckets(uint16_t* list, const ID& ids, uint32_t* tkey
     wave_sync();
     SORT_T(2);
     const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
-    if (wave_max_u32(max(max(h0, h1), max(h2, h3))) > kMaxBucket) return false;
+    if (wave_max_u32(max(max(h0, h1), max(h2, h3))) > kMaxBucket) {
+        if constexpr (OVER) {  // put the list back for the fallback
+            wave_sync();
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                const uint32_t g = lane * P + j;
+                if (g < len) list[g] = (uint16_t)(sd[j] & 0xFFFFu);
+            }
+            wave_sync();
+        }
+        return false;
+    }
     // exclusive scan of the 256 counts: bucket d occupies [hist[d], hist[d+1])
     const uint32_t sum = h0 + h1 + h2 + h3;
     uint32_t incl = sum;
@@ -338,13 +359,14 @@ __device__ bool sort_level_buckets(uint16_t* list, const ID& ids, uint32_t* tkey
     return true;
 }
 
-template <int P, typename ID>
+template <int P, bool OVER, typename ID>
 __device__ bool sort_level_buckets_dispatch(uint16_t* list, const ID& ids, uint32_t* tkey, uint32_t* hist,
                                             uint32_t len, uint32_t per_lane, uint32_t lane) {
     if constexpr (P >= 2 && P <= 32) {
-        if (per_lane == (uint32_t)P) return sort_level_buckets<P>(list, ids, tkey, hist, len, lane);
+        if (per_lane == (uint32_t)P) return sort_level_buckets<P, OVER>(list, ids, tkey, hist, len, lane);
     }
-    if constexpr (P > 2) return sort_level_buckets_dispatch<P / 2>(list, ids, tkey, hist, len, per_lane, lane);
+    if constexpr (P > 2)
+        return sort_level_buckets_dispatch<P / 2, OVER>(list, ids, tkey, hist, len, per_lane, lane);
     return false;
 }
 
@@ -434,11 +456,12 @@ __device__ void sort_level_radix(IT* list, IT* list2, const ID& ids, uint32_t* t
 template <int P, typename ID>
 __device__ void sort_level(uint16_t* list, const ID& ids, uint32_t* tkey, uint32_t* hist, uint32_t len,
                            uint32_t lane) {
+    constexpr bool kOver = P >= (int)kHistOverListMinP;  // the layout's choice for this class
     if (len <= 64) {
         sort_level_rank<uint16_t>(list, ids, len, lane);
     } else {
         const uint32_t per_lane = next_pow2((len + 63) / 64);
-        if (!sort_level_buckets_dispatch<P>(list, ids, tkey, hist, len, per_lane, lane)) {
+        if (!sort_level_buckets_dispatch<P, kOver>(list, ids, tkey, hist, len, per_lane, lane)) {
             wave_sync();
             sort_level_dispatch<P>(list, ids, len, per_lane, lane);
         }
@@ -452,30 +475,28 @@ __device__ void sort_level(uint16_t* list, const ID& ids, uint32_t* tkey, uint32
 
 extern __shared__ __align__(16) unsigned char smem[];
 
-// Finds the minimum count m of the k counters and lists the counters at m in
-// id order; state at LDS byte offset sbo.  `prev` is the level just
+// Finds the minimum count m of the counters and lists the slots at m in id
+// order; state at LDS byte offset sbo.  `prev` is the level just
 // exhausted: one pass finds the minimum and collects the counters at
 // prev + 1, the usual next level, and a second pass collects the true
 // minimum level when it differs.  Returns m << 32 | length.
 template <int P>
 __device__ __forceinline__ uint64_t level_lds_body(uint32_t sbo, const ChunkLayout& L, uint32_t prev,
                                                    uint32_t lane) {
-    const uint32_t k = L.k;
-    const uint32_t* cnt = (const uint32_t*)(smem + sbo + L.off_cnt);
+    const uint32_t S = L.slots;
+    const uint32_t* words = (const uint32_t*)(smem + sbo + L.off_table);
     uint16_t* list = (uint16_t*)(smem + sbo + L.off_list);
-    uint8_t* mark = (uint8_t*)(smem + sbo + L.off_mark);
     uint32_t* tkey = (uint32_t*)(smem + sbo + L.off_tkey);
     uint32_t* hist = (uint32_t*)(smem + sbo + L.off_hist);
-    const CounterIds<uint16_t> ids{(const uint64_t*)(smem + sbo + L.off_table),
-                                   (const uint16_t*)(smem + sbo + L.off_hpos)};
+    const SlotIds ids{(const uint64_t*)(smem + sbo + L.off_table)};
     const uint32_t guess = prev + 1u;
     uint32_t mn = 0xFFFFFFFFu, len = 0;
-    for (uint32_t b = 0; b < k; b += 4 * kWave) {
+    for (uint32_t b = 0; b < S; b += 4 * kWave) {
         uint32_t cv[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t s = b + j * kWave + lane;
-            cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
+            cv[j] = s < S ? slot_count(words, s) : 0xFFFFFFFFu;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -489,12 +510,12 @@ __device__ __forceinline__ uint64_t level_lds_body(uint32_t sbo, const ChunkLayo
     const uint32_t m = uniform(wave_min_u32(mn));
     if (m != guess) {
         len = 0;
-        for (uint32_t b = 0; b < k; b += 4 * kWave) {
+        for (uint32_t b = 0; b < S; b += 4 * kWave) {
             uint32_t cv[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const uint32_t s = b + j * kWave + lane;
-                cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
+                cv[j] = s < S ? slot_count(words, s) : 0xFFFFFFFFu;
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -507,9 +528,6 @@ __device__ __forceinline__ uint64_t level_lds_body(uint32_t sbo, const ChunkLayo
     }
     wave_sync();
     sort_level<P>(list, ids, tkey, hist, len, lane);
-    // the histogram overlaid the victim marks: zero them again
-    for (uint32_t i = 4 * lane; i < kHistBytes; i += 4 * kWave) *(uint32_t*)(mark + i) = 0u;
-    wave_sync();
     return ((uint64_t)m << 32) | len;
 }
 
@@ -529,22 +547,22 @@ __device__ __attribute__((noinline)) uint64_t build_level_lds(uint32_t sbo, Chun
 // here (this path waits on device memory, not on instruction issue).
 __device__ __forceinline__ uint64_t build_level_global(unsigned char* sb, unsigned char* lds,
                                                        const ChunkLayout& L, uint32_t prev, uint32_t lane) {
-    const uint32_t k = L.k;
-    const uint32_t* cnt = (const uint32_t*)(sb + L.off_cnt);
+    const uint32_t S = L.slots;
+    const uint32_t* words = (const uint32_t*)(sb + L.off_table);
     uint32_t* list = (uint32_t*)(sb + L.off_list);
     uint32_t* list2 = (uint32_t*)(sb + L.off_list2);
     uint32_t* tkey = (uint32_t*)(sb + L.off_tkey);
     uint32_t* tkey2 = (uint32_t*)(sb + L.off_tkey2);
     uint32_t* hist = (uint32_t*)(lds + L.off_hist);
-    const CounterIds<uint32_t> ids{(const uint64_t*)(sb + L.off_table), (const uint32_t*)(sb + L.off_hpos)};
+    const SlotIds ids{(const uint64_t*)(sb + L.off_table)};
     const uint32_t guess = prev + 1u;
     uint32_t mn = 0xFFFFFFFFu, len = 0;
-    for (uint32_t b = 0; b < k; b += 4 * kWave) {
+    for (uint32_t b = 0; b < S; b += 4 * kWave) {
         uint32_t cv[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t s = b + j * kWave + lane;
-            cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
+            cv[j] = s < S ? slot_count(words, s) : 0xFFFFFFFFu;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -558,12 +576,12 @@ __device__ __forceinline__ uint64_t build_level_global(unsigned char* sb, unsign
     const uint32_t m = uniform(wave_min_u32(mn));
     if (m != guess) {
         len = 0;
-        for (uint32_t b = 0; b < k; b += 4 * kWave) {
+        for (uint32_t b = 0; b < S; b += 4 * kWave) {
             uint32_t cv[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const uint32_t s = b + j * kWave + lane;
-                cv[j] = s < k ? cnt[s] : 0xFFFFFFFFu;
+                cv[j] = s < S ? slot_count(words, s) : 0xFFFFFFFFu;
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -588,17 +606,27 @@ __device__ __forceinline__ uint64_t build_level_global(unsigned char* sb, unsign
 // ---------------------------------------------------------------------------
 
 // Four consecutive items at idx (a multiple of 4), zero at and beyond stop.
+// The input is read once: loads are marked non-temporal so that the stream
+// does not push the blocks' error scratch out of the L2.
+#ifndef PSS_INPUT_TEMPORAL
+#define PSS_NT_LOAD(p) __builtin_nontemporal_load(p)
+#else
+#define PSS_NT_LOAD(p) (*(p))
+#endif
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ uint4 load4(const uint32_t* __restrict__ items, uint64_t idx, uint64_t n, uint64_t stop,
                                        int vec_ok) {
     uint4 v = make_uint4(0u, 0u, 0u, 0u);
     if (idx >= stop) return v;
     if (vec_ok && idx + 3 < n) {
-        v = *(const uint4*)(items + idx);
+        const u32x4_t t = PSS_NT_LOAD((const u32x4_t*)(items + idx));
+        v = make_uint4(t[0], t[1], t[2], t[3]);
     } else {
-        if (idx < n) v.x = items[idx];
-        if (idx + 1 < n) v.y = items[idx + 1];
-        if (idx + 2 < n) v.z = items[idx + 2];
-        if (idx + 3 < n) v.w = items[idx + 3];
+        if (idx < n) v.x = PSS_NT_LOAD(items + idx);
+        if (idx + 1 < n) v.y = PSS_NT_LOAD(items + idx + 1);
+        if (idx + 2 < n) v.z = PSS_NT_LOAD(items + idx + 2);
+        if (idx + 3 < n) v.w = PSS_NT_LOAD(items + idx + 3);
     }
     return v;
 }
@@ -629,47 +657,39 @@ __device__ __forceinline__ void store_half(uint32_t* ring, uint64_t tile, const 
 // P: registers per lane for the in-register level sort (LDS-resident state);
 // G: the state at sb lives in global memory with 32-bit indices (k whose
 // state does not fit LDS), else sb is in LDS.  lds holds the input ring and
-// the per-window arrays.  Writes entries [0, size) to o_item/o_cnt/o_err and
-// the header to *o_size, *o_min.
+// the per-window arrays; errs is the block's error scratch (one word per
+// slot).  Writes entries [0, size) to o_item/o_cnt/o_err and the header to
+// *o_size, *o_min.
 template <int P, bool G>
 __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ items, uint64_t n, uint64_t begin,
                                                 uint64_t end, const ChunkLayout& L, int vec_ok, unsigned char* sb,
-                                                unsigned char* lds, uint32_t* __restrict__ o_item,
-                                                uint32_t* __restrict__ o_cnt, uint32_t* __restrict__ o_err,
-                                                uint32_t* __restrict__ o_size, uint32_t* __restrict__ o_min) {
+                                                unsigned char* lds, uint32_t* __restrict__ errs,
+                                                uint32_t* __restrict__ o_item, uint32_t* __restrict__ o_cnt,
+                                                uint32_t* __restrict__ o_err, uint32_t* __restrict__ o_size,
+                                                uint32_t* __restrict__ o_min) {
     using idx_t = typename std::conditional<G, uint32_t, uint16_t>::type;
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t k = L.k;
     const uint32_t T = L.tsize;
+    const uint32_t S = L.slots;
     const uint32_t NB = L.nbuckets;
+    // the counters: slot s holds key | count << 32
     uint64_t* table = (uint64_t*)(sb + L.off_table);
+    uint32_t* words = (uint32_t*)(sb + L.off_table);  // count of slot s: words[2 s + 1]
     const uint4* tbl4 = (const uint4*)(sb + L.off_table);
-    uint32_t* cnt = (uint32_t*)(sb + L.off_cnt);
-    uint32_t* err = o_err;  // errors live in the output array; ids are the table keys
-    idx_t* hpos = (idx_t*)(sb + L.off_hpos);
     idx_t* list = (idx_t*)(sb + L.off_list);
-    const CounterIds<idx_t> ids{table, hpos};
-    uint8_t* mark = (uint8_t*)(sb + L.off_mark);
-    uint32_t* tkey = (uint32_t*)(sb + L.off_tkey);
-    idx_t* list2 = (idx_t*)(sb + L.off_list2);
-    uint32_t* tkey2 = (uint32_t*)(sb + L.off_tkey2);
+    const SlotIds ids{table};
     uint32_t* ring = (uint32_t*)(lds + L.off_ring);
-    uint32_t* vslot = (uint32_t*)(lds + L.off_vslot);
-    uint32_t* vhpos = (uint32_t*)(lds + L.off_vhpos);
-    // the sort histogram: in LDS beside the ring (HBM state) or over the
-    // victim marks (LDS state)
-    uint32_t* hist = G ? (uint32_t*)(lds + L.off_hist) : (uint32_t*)(sb + L.off_hist);
     const uint4* stash4 = tbl4 + T / 2;
 
-    for (uint32_t i = lane; i < T + kStash; i += kWave) table[i] = 0ull;
-    for (uint32_t i = lane; i < k; i += kWave) mark[i] = 0;
+    for (uint32_t i = lane; i < S; i += kWave) table[i] = 0ull;
 
     // Wave-uniform state.  Every update goes through uniform() so the compiler
     // keeps it in scalar registers and every loop that contains wave-wide
     // operations (ballot, DPP, readlane, shuffles) has a uniform exit.
     uint32_t size = 0, full = 0, failed = 0;
-    uint32_t stash_live = 0;  // live entries in the stash
-    // minimum level: count m and its listed counters [list_ptr, list_len)
+    uint32_t stash_live = 0;  // counters in the stash
+    // minimum level: count m and its listed slots [list_ptr, list_len)
     uint32_t m = 0, list_len = 0, list_ptr = 0;
     uint32_t last_slow = 0;
 
@@ -699,28 +719,38 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
             KSTAT_ADD(10, 1);
         }
         const unsigned long long tw = KSTAT_NOW();
+        // the stash, lane i holding slot T + i: its keys serve this window's
+        // lookups
+        uint32_t skey = 0;
+        bool slive = false;
         if (stash_live) {
-            // move stash entries back to a bucket with room (deletions free
-            // slots all the time); lane i handles stash slot i
-            const uint32_t si = T + lane;
-            const uint64_t e = table[si];
-            const uint32_t key = (uint32_t)e, tag = (uint32_t)(e >> 32);
-            const uint32_t s1 = home_bucket(key, NB), s2 = alt_bucket(key, NB, s1);
-            const Bucket B1 = load_bucket(tbl4, s1), B2 = load_bucket(tbl4, s2);
-            const uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2);
-            bool moved = false;
-            if (live_tag(tag) && (e1 | e2)) {
-                const uint32_t dst = __builtin_popcount(e1) >= __builtin_popcount(e2)
-                                         ? kBucketSlots * s1 + (uint32_t)__builtin_ctz(e1)
-                                         : kBucketSlots * s2 + (uint32_t)__builtin_ctz(e2);
-                if (atomicCAS((unsigned long long*)&table[dst], 0ull, (unsigned long long)e) == 0ull) {
-                    table[si] = 0ull;
-                    hpos[tag - 1u] = (idx_t)dst;
-                    moved = true;
+            const uint64_t e = table[T + lane];
+            skey = (uint32_t)e;
+            const uint32_t c = (uint32_t)(e >> 32);
+            slive = live_tag(c);
+            // move counters back to a bucket with room (deletions free slots
+            // all the time).  A counter at the minimum level stays: it may be
+            // listed as a victim by slot.
+            const bool cand = slive && (!full || c != m);
+            if (ballot(cand)) {
+                const uint32_t s1 = home_bucket(skey, NB), s2 = alt_bucket(skey, NB, s1);
+                const Bucket B1 = load_bucket(tbl4, s1), B2 = load_bucket(tbl4, s2);
+                const uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2);
+                bool moved = false;
+                if (cand && (e1 | e2)) {
+                    const uint32_t dst = __builtin_popcount(e1) >= __builtin_popcount(e2)
+                                             ? kBucketSlots * s1 + (uint32_t)__builtin_ctz(e1)
+                                             : kBucketSlots * s2 + (uint32_t)__builtin_ctz(e2);
+                    if (atomicCAS((unsigned long long*)&table[dst], 0ull, (unsigned long long)e) == 0ull) {
+                        errs[dst] = errs[T + lane];
+                        table[T + lane] = 0ull;
+                        moved = true;
+                    }
                 }
+                slive = slive && !moved;
+                stash_live = uniform(stash_live - popc64(ballot(moved)));
+                wave_sync();
             }
-            stash_live = uniform(stash_live - popc64(ballot(moved)));
-            wave_sync();
         }
 
         const uint32_t wl = (uint32_t)((end - pos) < kWave ? (end - pos) : kWave);
@@ -732,14 +762,13 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         // clamped indices: no divergent branch may separate the wave-wide
         // operations of the victim loop below.
         bool vinb = false;
-        uint32_t vs = 0, vcnt = 0, vhp = 0;
+        uint32_t vs = 0, vcnt = 0;
         auto fetch_victims = [&]() {
             const uint32_t li = list_ptr + lane;
             vinb = li < list_len;
             const uint32_t e = list[vinb ? li : 0u];
             vs = vinb ? e : 0u;
-            vcnt = cnt[vs];
-            vhp = hpos[vs];
+            vcnt = words[2 * vs + 1];
         };
         const bool early = last_slow && full && list_ptr < list_len;
         if (early) fetch_victims();
@@ -753,24 +782,17 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         Bucket B1 = load_bucket(tbl4, b1), B2 = load_bucket(tbl4, b2);
         {
             const uint32_t h1 = match_mask(B1, x), h2 = match_mask(B2, x);
-            const uint32_t tag = h1 ? tag_at(B1, (uint32_t)__builtin_ctz(h1))
-                                    : tag_at(B2, (uint32_t)__builtin_ctz(h2 | (1u << kBucketSlots)) &
-                                                     (kBucketSlots - 1));
+            slot = h1 ? kBucketSlots * b1 + (uint32_t)__builtin_ctz(h1)
+                      : kBucketSlots * b2 + ((uint32_t)__builtin_ctz(h2 | (1u << kBucketSlots)) & (kBucketSlots - 1));
             hit = valid && (h1 | h2) != 0u;
-            slot = tag - 1u;
         }
         KSTAT_ADD(16, stash_live ? 1 : 0);
-        if (stash_live) {
-            for (uint32_t i = 0; i < kStash / 2; ++i) {
-                const uint4 e = stash4[i];
-                if (e.x == x && live_tag(e.y)) {
-                    hit = valid;
-                    slot = e.y - 1u;
-                }
-                if (e.z == x && live_tag(e.w)) {
-                    hit = valid;
-                    slot = e.w - 1u;
-                }
+        // the stash's live keys, one by one from the lanes holding them
+        for (uint64_t sm = ballot(slive); sm; sm &= sm - 1) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(sm);
+            if (x == (uint32_t)__builtin_amdgcn_readlane((int)skey, (int)j)) {
+                hit = valid;
+                slot = T + j;
             }
         }
         miss = valid && !hit;
@@ -779,7 +801,7 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         KSTAT_ADD(15, KSTAT_NOW() - tw);
         if (missmask == 0) {
             // all hits: increments commute
-            if (hit) atomicAdd(&cnt[slot], 1u);
+            if (hit) atomicAdd(&words[2 * slot + 1], 1u);
             pos += wl;
             last_slow = 0;
             KSTAT_ADD(1, 1);
@@ -788,7 +810,7 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         }
         last_slow = 1;
 
-        // 2. group unmonitored items by value: one pending hash entry per value,
+        // 2. group unmonitored items by value: one claimed slot per value,
         //    tagged with the lowest lane holding it
         const unsigned long long tp = KSTAT_NOW();
         //    Each lane claims a free slot of its emptier bucket (else of the
@@ -799,9 +821,10 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         //    (the slot leaves the lane's view).  Lanes holding equal values
         //    see the same buckets and the same outcomes, so they pick the same
         //    slots.  Every lost swap removes a slot from the view, so the loop
-        //    ends within 16 + 64 rounds.
+        //    ends within 16 + 64 rounds.  The claimed slot becomes the new
+        //    counter if the item is installed.
         if (miss) {
-            const uint64_t mine = make_entry(x, kTagPend | lane);
+            const uint64_t mine = make_entry(x, kTagPend + lane);
             uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2);
             uint32_t steps = 0;
             for (;;) {
@@ -815,11 +838,11 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                     uint32_t fe = kNone;
                     for (uint32_t i = 0; i < kStash / 2; ++i) {
                         const uint4 e = stash4[i];
-                        if (e.x == x && (e.y & kTagPend)) {
+                        if (e.x == x && e.y >= kTagPend) {
                             h = T + 2 * i;
                             join = true;
                         }
-                        if (e.z == x && (e.w & kTagPend)) {
+                        if (e.z == x && e.w >= kTagPend) {
                             h = T + 2 * i + 1;
                             join = true;
                         }
@@ -839,14 +862,14 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                         hp = h;
                         break;
                     }
-                    join = (uint32_t)old == x && ((uint32_t)(old >> 32) & kTagPend);
+                    join = (uint32_t)old == x && (uint32_t)(old >> 32) >= kTagPend;
                     if (!join && h < T) {  // taken by another value
                         const uint32_t bit = 1u << (h % kBucketSlots);
                         if (h / kBucketSlots == b1) e1 &= ~bit; else e2 &= ~bit;
                     }
                 }
                 if (join) {
-                    atomicMin(((uint32_t*)&table[h]) + 1, kTagPend | lane);
+                    atomicMin(&words[2 * h + 1], kTagPend + lane);
                     hp = h;
                     break;
                 }
@@ -892,17 +915,17 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                     uint32_t len = 0;
                     const unsigned long long tsrt = KSTAT_NOW();
                     if constexpr (G) {
-                        const uint64_t r = build_level_global(sb, lds, L, m, lane);
-                        m = uniform((uint32_t)(r >> 32));
-                        len = uniform((uint32_t)r);
+                        const uint64_t rr = build_level_global(sb, lds, L, m, lane);
+                        m = uniform((uint32_t)(rr >> 32));
+                        len = uniform((uint32_t)rr);
                     } else {
-                        uint64_t r;
+                        uint64_t rr;
                         if constexpr (P >= 16)
-                            r = build_level_lds<P>((uint32_t)(sb - smem), L, m, lane);
+                            rr = build_level_lds<P>((uint32_t)(sb - smem), L, m, lane);
                         else
-                            r = level_lds_body<P>((uint32_t)(sb - smem), L, m, lane);
-                        m = uniform((uint32_t)(r >> 32));
-                        len = uniform((uint32_t)r);
+                            rr = level_lds_body<P>((uint32_t)(sb - smem), L, m, lane);
+                        m = uniform((uint32_t)(rr >> 32));
+                        len = uniform((uint32_t)rr);
                     }
                     list_len = len;
                     list_ptr = 0;
@@ -914,17 +937,19 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
             if (failed) continue;
             avail = popc64(vmask);
             vr = mbcnt(vmask);
-            if (vv) {
-                vslot[vr] = vs;
-                vhpos[vr] = vhp;
-                mark[vs] = (uint8_t)(vr + 1);
-            }
+            // tag them with their rank for the conflict test (their count is m)
+            if (vv) words[2 * vs + 1] = kTagVict + vr;
         }
         wave_sync();
         KSTAT_ADD(6, KSTAT_NOW() - tv);
 
-        const uint32_t rep = miss ? (((const volatile uint32_t*)&table[hp])[1] & 63u) : lane;
-        const uint32_t jmark = (hit && full) ? mark[slot] : 0u;
+        const uint32_t rep = miss ? (((const volatile uint32_t*)words)[2 * hp + 1] - kTagPend) : lane;
+        // a hit on a counter tagged as the j-th victim: jmark = j + 1
+        uint32_t jmark = 0;
+        if (hit && full) {
+            const uint32_t c = ((const volatile uint32_t*)words)[2 * slot + 1];
+            jmark = (c >= kTagVict && c < kTagPend) ? c - kTagVict + 1u : 0u;
+        }
         const uint64_t newmask = ballot(miss && rep == lane);
         const bool newf = (newmask >> lane) & 1ull;
         const uint32_t r = popc64(newmask);
@@ -946,40 +971,41 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         }
         const bool in = lane < p;
 
-        // 5. apply the prefix
-        uint32_t myslot = 0;
-        if (in && hit) atomicAdd(&cnt[slot], 1u);
+        // 5. apply the prefix: the first rp victims empty their slots, the
+        //    others get their count m back; then hits add 1; a new item
+        //    becomes the counter in its claimed slot (count 1, or m + 1 with
+        //    error m when it replaces a victim); a repeat adds 1 to its
+        //    value's new counter; claims past the prefix are released
+        const uint64_t inmask = (p >= kWave) ? ~0ull : ((1ull << p) - 1ull);
+        const uint32_t rp = popc64(newmask & inmask);
+        if (full) {
+            if (vv) {
+                if (vr < rp)
+                    table[vs] = 0ull;
+                else
+                    words[2 * vs + 1] = m;
+            }
+            wave_sync();
+        }
+        if (in && hit) atomicAdd(&words[2 * slot + 1], 1u);
         if (newf) {
             if (in) {
-                if (!full) {
-                    myslot = size + nrank;
-                    cnt[myslot] = 1u;
-                    err[myslot] = 0u;
-                } else {
-                    myslot = vslot[nrank];
-                    table[vhpos[nrank]] = 0ull;  // the victim's entry becomes empty
-                    cnt[myslot] = m + 1u;
-                    err[myslot] = m;
-                }
-                hpos[myslot] = (idx_t)hp;
-                table[hp] = make_entry(x, myslot + 1u);
+                errs[hp] = full ? m : 0u;
+                table[hp] = make_entry(x, full ? m + 1u : 1u);
             } else {
-                table[hp] = 0ull;  // not applied: release the claim
+                table[hp] = 0ull;
             }
         }
         const bool repeat = in && miss && !newf;
         if (ballot(repeat)) {
             wave_sync();
-            const uint32_t rslot = (uint32_t)__shfl((int)myslot, (int)rep);
-            if (repeat) atomicAdd(&cnt[rslot], 1u);
+            const uint32_t rslot = (uint32_t)__shfl((int)hp, (int)rep);
+            if (repeat) atomicAdd(&words[2 * rslot + 1], 1u);
         }
-        if (vv) mark[vs] = 0;
 
-        const uint64_t inmask = (p >= kWave) ? ~0ull : ((1ull << p) - 1ull);
-        const uint32_t rp = popc64(newmask & inmask);
-        // stash occupancy: applied new items placed there, evicted victims removed from there
+        // stash occupancy: new counters placed there, evicted victims removed from there
         const uint32_t sadd = popc64(ballot(newf && in && hp >= T));
-        const uint32_t sdel = popc64(ballot(vv && vr < rp && vhp >= T));
+        const uint32_t sdel = popc64(ballot(vv && vr < rp && vs >= T));
         stash_live = uniform(stash_live + sadd - sdel);
         if (!full) {
             size = uniform(size + rp);
@@ -1001,7 +1027,8 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
     KSTAT_ADD(12, KSTAT_NOW() - t_start);
     KSTAT_FLUSH();
 
-    // write the summary and its minimum (0 while fewer than k counters are used)
+    // write the summary, compacted from the slots, and its minimum (0 while
+    // fewer than k counters are used)
     wave_sync();
     if (failed) {
         if (lane == 0) {
@@ -1010,25 +1037,32 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         }
         return;
     }
-    uint32_t mo = 0;
-    if (full) {
-        uint32_t mn = 0xFFFFFFFFu;
-        for (uint32_t s = lane; s < k; s += kWave) mn = min(mn, cnt[s]);
-        mo = wave_min_u32(mn);
+    uint32_t mn = 0xFFFFFFFFu, outn = 0;
+    for (uint32_t b = 0; b < S; b += kWave) {
+        const uint32_t s = b + lane;
+        const uint64_t e = s < S ? table[s] : 0ull;
+        const uint32_t c = (uint32_t)(e >> 32);
+        const bool live = s < S && live_tag(c);
+        const uint64_t bm = ballot(live);
+        if (live) {
+            const uint32_t o = outn + mbcnt(bm);
+            o_item[o] = (uint32_t)e;
+            o_cnt[o] = c;
+            o_err[o] = errs[s];
+            mn = min(mn, c);
+        }
+        outn = uniform(outn + popc64(bm));
     }
-    for (uint32_t s = lane; s < size; s += kWave) {  // errors are already in place
-        o_item[s] = ids(s);
-        o_cnt[s] = cnt[s];
-    }
+    const uint32_t mo = full ? wave_min_u32(mn) : 0u;
     if (lane == 0) {
-        *o_size = size;
+        *o_size = outn == size ? size : kBlockFailed;  // the slots hold exactly the counters
         *o_min = mo;
     }
 }
 
 // One wave per block c of C: [floor(c n / C), floor((c+1) n / C)) (Algorithm
 // 1's block bounds, 64-bit products, n < 2^32).  G: state slab gstate +
-// c * state_bytes.
+// c * state_bytes.  Error scratch of block c: errs + c * err_stride.
 template <int P, bool G>
 __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __restrict__ items, uint64_t n,
                                                            uint32_t chunks, ChunkLayout L, int vec_ok,
@@ -1037,22 +1071,24 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
                                                            uint32_t* __restrict__ o_err,
                                                            uint32_t* __restrict__ o_size,
                                                            uint32_t* __restrict__ o_min,
-                                                           unsigned char* __restrict__ gstate) {
+                                                           unsigned char* __restrict__ gstate,
+                                                           uint32_t* __restrict__ errs) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t c = blockIdx.x;
     unsigned char* sb = G ? gstate + (size_t)c * L.state_bytes : smem;
     const uint64_t begin = (uint64_t)c * n / chunks;
     const uint64_t end = (uint64_t)(c + 1) * n / chunks;
     const uint64_t ob = (uint64_t)c * L.k;
-    summarize_block<P, G>(items, n, begin, end, L, vec_ok, sb, smem, o_item + ob, o_cnt + ob, o_err + ob, o_size + c,
-                          o_min + c);
+    summarize_block<P, G>(items, n, begin, end, L, vec_ok, sb, smem, errs + (size_t)c * L.err_stride, o_item + ob,
+                          o_cnt + ob, o_err + ob, o_size + c, o_min + c);
 }
 
 // Batched form: every wave of a persistent grid takes blocks from a queue
 // (one counter per launch, zeroed before it) until the list is exhausted.
 // Blocks of one launch share P (their k fall in one size class); each block
-// carries its own stream, bounds, k and hash load factor.  W waves per
-// workgroup, each with its own LDS slab of lds_stride bytes.
+// carries its own stream, bounds, k, hash load factor and error scratch
+// (errs + eoff).  W waves per workgroup, each with its own LDS slab of
+// lds_stride bytes.
 template <int P, int W>
 __global__ __launch_bounds__(64 * W) void batch_blocks_kernel(const BatchBlock* __restrict__ blocks,
                                                               uint32_t nblocks, uint32_t* __restrict__ queue,
@@ -1060,7 +1096,8 @@ __global__ __launch_bounds__(64 * W) void batch_blocks_kernel(const BatchBlock* 
                                                               uint32_t* __restrict__ o_cnt,
                                                               uint32_t* __restrict__ o_err,
                                                               uint32_t* __restrict__ o_size,
-                                                              uint32_t* __restrict__ o_min) {
+                                                              uint32_t* __restrict__ o_min,
+                                                              uint32_t* __restrict__ errs) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* lds = smem + (threadIdx.x / kWave) * lds_stride;
     const uint32_t lane = lane_id();
@@ -1072,33 +1109,34 @@ __global__ __launch_bounds__(64 * W) void batch_blocks_kernel(const BatchBlock* 
         const BatchBlock bb = blocks[b];
         const ChunkLayout L = ChunkLayout::make(bb.k, false, bb.slots_x16);
         const int vec_ok = ((uintptr_t)bb.items & 15u) == 0;
-        summarize_block<P, false>(bb.items, bb.n, bb.begin, bb.end, L, vec_ok, lds, lds, o_item + bb.out,
-                                  o_cnt + bb.out, o_err + bb.out, o_size + b, o_min + b);
+        summarize_block<P, false>(bb.items, bb.n, bb.begin, bb.end, L, vec_ok, lds, lds, errs + bb.eoff,
+                                  o_item + bb.out, o_cnt + bb.out, o_err + bb.out, o_size + b, o_min + b);
         wave_sync();  // the slab is reused by the next block
     }
 }
 
 template <int P, int W>
 static hipError_t launch_batch_pw(const BatchBlock* blocks, uint32_t nblocks, uint32_t* queue, uint32_t lds_stride,
-                                  uint32_t grid, const BlockSummaries& out, hipStream_t stream) {
+                                  uint32_t grid, const BlockSummaries& out, uint32_t* errs, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     const uint32_t lds = W * lds_stride;
     hipFuncSetAttribute((const void*)batch_blocks_kernel<P, W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((batch_blocks_kernel<P, W>), dim3(grid), dim3(64 * W), lds, stream, blocks, nblocks, queue,
-                       lds_stride, out.item, out.cnt, out.err, out.size, out.min);
+                       lds_stride, out.item, out.cnt, out.err, out.size, out.min, errs);
     return hipGetLastError();
 }
 
 template <int P>
 static hipError_t launch_batch_p(const BatchBlock* blocks, uint32_t nblocks, uint32_t* queue, uint32_t lds_stride,
-                                 uint32_t waves_per_group, uint32_t grid, const BlockSummaries& out,
+                                 uint32_t waves_per_group, uint32_t grid, const BlockSummaries& out, uint32_t* errs,
                                  hipStream_t stream) {
     switch (waves_per_group) {
-    case 1: return launch_batch_pw<P, 1>(blocks, nblocks, queue, lds_stride, grid, out, stream);
+    case 1: return launch_batch_pw<P, 1>(blocks, nblocks, queue, lds_stride, grid, out, errs, stream);
     case 2:
-        if constexpr (P <= 16) return launch_batch_pw<P, 2>(blocks, nblocks, queue, lds_stride, grid, out, stream);
+        if constexpr (P <= 16) return launch_batch_pw<P, 2>(blocks, nblocks, queue, lds_stride, grid, out, errs, stream);
         return hipErrorInvalidValue;
     case 4:
-        if constexpr (P <= 8) return launch_batch_pw<P, 4>(blocks, nblocks, queue, lds_stride, grid, out, stream);
+        if constexpr (P <= 8) return launch_batch_pw<P, 4>(blocks, nblocks, queue, lds_stride, grid, out, errs, stream);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
@@ -1106,16 +1144,17 @@ static hipError_t launch_batch_p(const BatchBlock* blocks, uint32_t nblocks, uin
 
 hipError_t launch_batch_blocks(const BatchBlock* blocks, uint32_t nblocks, uint32_t* queue, uint32_t sort_lanes,
                                uint32_t lds_stride, uint32_t waves_per_group, uint32_t grid,
-                               const BlockSummaries& out, hipStream_t stream) {
+                               const BlockSummaries& out, uint32_t* errs, hipStream_t stream) {
     if (nblocks == 0) return hipSuccess;
+    if (!errs) return hipErrorInvalidValue;
     switch (sort_lanes) {
     case 1:
-    case 2: return launch_batch_p<2>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, stream);
-    case 4: return launch_batch_p<4>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, stream);
-    case 8: return launch_batch_p<8>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, stream);
-    case 16: return launch_batch_p<16>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, stream);
-    case 32: return launch_batch_p<32>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, stream);
-    case 64: return launch_batch_p<64>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, stream);
+    case 2: return launch_batch_p<2>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, errs, stream);
+    case 4: return launch_batch_p<4>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, errs, stream);
+    case 8: return launch_batch_p<8>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, errs, stream);
+    case 16: return launch_batch_p<16>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, errs, stream);
+    case 32: return launch_batch_p<32>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, errs, stream);
+    case 64: return launch_batch_p<64>(blocks, nblocks, queue, lds_stride, waves_per_group, grid, out, errs, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1133,11 +1172,12 @@ extern "C" int pss_debug_kstats(unsigned long long* out, int reset) {
 
 template <int P, bool G>
 static hipError_t launch_p(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L, int vec_ok,
-                           const BlockSummaries& out, unsigned char* gstate, hipStream_t stream) {
+                           const BlockSummaries& out, unsigned char* gstate, uint32_t* errs, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     hipFuncSetAttribute((const void*)chunk_summary_kernel<P, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)L.lds_bytes);
     hipLaunchKernelGGL((chunk_summary_kernel<P, G>), dim3(chunks), dim3(64), L.lds_bytes, stream, d_items, n, chunks,
-                       L, vec_ok, out.item, out.cnt, out.err, out.size, out.min, gstate);
+                       L, vec_ok, out.item, out.cnt, out.err, out.size, out.min, gstate, errs);
     return hipGetLastError();
 }
 
@@ -1148,20 +1188,22 @@ ChunkLayout chunk_layout(uint32_t k, size_t lds_max) {
 }
 
 hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L,
-                                const BlockSummaries& out, unsigned char* gstate, hipStream_t stream) {
+                                const BlockSummaries& out, unsigned char* gstate, uint32_t* errs,
+                                hipStream_t stream) {
     const int vec_ok = ((uintptr_t)d_items & 15u) == 0;
+    if (!errs) return hipErrorInvalidValue;
     if (L.global_state) {
         if (!gstate) return hipErrorInvalidValue;
-        return launch_p<1, true>(d_items, n, chunks, L, vec_ok, out, gstate, stream);
+        return launch_p<1, true>(d_items, n, chunks, L, vec_ok, out, gstate, errs, stream);
     }
     switch (sort_lanes_per_k(L.k)) {
     case 1:
-    case 2: return launch_p<2, false>(d_items, n, chunks, L, vec_ok, out, nullptr, stream);
-    case 4: return launch_p<4, false>(d_items, n, chunks, L, vec_ok, out, nullptr, stream);
-    case 8: return launch_p<8, false>(d_items, n, chunks, L, vec_ok, out, nullptr, stream);
-    case 16: return launch_p<16, false>(d_items, n, chunks, L, vec_ok, out, nullptr, stream);
-    case 32: return launch_p<32, false>(d_items, n, chunks, L, vec_ok, out, nullptr, stream);
-    case 64: return launch_p<64, false>(d_items, n, chunks, L, vec_ok, out, nullptr, stream);
+    case 2: return launch_p<2, false>(d_items, n, chunks, L, vec_ok, out, nullptr, errs, stream);
+    case 4: return launch_p<4, false>(d_items, n, chunks, L, vec_ok, out, nullptr, errs, stream);
+    case 8: return launch_p<8, false>(d_items, n, chunks, L, vec_ok, out, nullptr, errs, stream);
+    case 16: return launch_p<16, false>(d_items, n, chunks, L, vec_ok, out, nullptr, errs, stream);
+    case 32: return launch_p<32, false>(d_items, n, chunks, L, vec_ok, out, nullptr, errs, stream);
+    case 64: return launch_p<64, false>(d_items, n, chunks, L, vec_ok, out, nullptr, errs, stream);
     default: return hipErrorInvalidValue;
     }
 }

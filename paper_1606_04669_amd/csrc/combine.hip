@@ -295,6 +295,7 @@ __global__ __launch_bounds__(kCombineThreads) void batch_combine_kernel(const Ba
 
 hipError_t launch_batch_combine(const BatchNode* nodes, uint32_t count, uint32_t kmax, const BlockSummaries& base,
                                 hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     if (count == 0) return hipSuccess;
     const uint32_t lds = combine_lds_bytes(kmax, false);
     hipFuncSetAttribute((const void*)batch_combine_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -322,6 +323,7 @@ __global__ __launch_bounds__(kCombineThreads) void serve_fold_kernel(const Serve
 
 hipError_t launch_serve_fold(const ServeFold* f, uint32_t count, uint32_t kmax, const WideSummary& pool,
                              const BlockSummaries& blocks, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     if (count == 0) return hipSuccess;
     const uint32_t lds = combine_lds_bytes(kmax, true);
     hipFuncSetAttribute((const void*)serve_fold_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -340,6 +342,7 @@ size_t combine_scratch_bytes(uint32_t k, bool wide) {
 
 hipError_t launch_combine_level(const BlockSummaries& v, uint32_t k, uint32_t count, uint32_t step, bool in_lds,
                                 unsigned char* scratch, uint32_t slabs, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     if (step >= count) return hipSuccess;
     // pairs (a, a + step) with a = 2 step j and a + step < count
     const uint32_t pairs = (uint32_t)(((uint64_t)count - step + 2ull * step - 1) / (2ull * step));
@@ -361,6 +364,7 @@ hipError_t launch_combine_level(const BlockSummaries& v, uint32_t k, uint32_t co
 
 hipError_t launch_fold(const WideSummary& dst, const BlockSummaries& src, uint32_t k, bool in_lds,
                        unsigned char* scratch, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     const CombineLds<uint64_t> L = CombineLds<uint64_t>::make(k);
     if (in_lds) {
         const uint32_t lds = L.big_bytes + L.small_bytes;
@@ -377,6 +381,7 @@ hipError_t launch_fold(const WideSummary& dst, const BlockSummaries& src, uint32
 
 hipError_t launch_merge(const WideSummary& dst, const WideSummary& src, uint32_t k, bool in_lds,
                         unsigned char* scratch, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     const CombineLds<uint64_t> L = CombineLds<uint64_t>::make(k);
     if (in_lds) {
         const uint32_t lds = L.big_bytes + L.small_bytes;

@@ -134,6 +134,7 @@ __global__ __launch_bounds__(kExtractThreads) void batch_extract_kernel(const Ba
 
 hipError_t launch_batch_extract(const BatchReport* reps, uint32_t count, uint32_t kmax, const BlockSummaries& base,
                                 DevEntry* out, uint32_t* out_count, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     if (count == 0) return hipSuccess;
     const uint32_t lds = extract_lds_bytes(kmax);
     hipFuncSetAttribute((const void*)batch_extract_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -160,6 +161,7 @@ __global__ __launch_bounds__(kExtractThreads) void serve_query_kernel(const Serv
 
 hipError_t launch_serve_query(const ServeQuery* q, uint32_t count, uint32_t kmax, const WideSummary& pool,
                               DevEntry* out, uint32_t* out_count, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     if (count == 0) return hipSuccess;
     const uint32_t lds = extract_lds_bytes(kmax);
     hipFuncSetAttribute((const void*)serve_query_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -173,6 +175,7 @@ __global__ void zero_words_kernel(uint32_t* p, uint32_t count) {
 }
 
 hipError_t launch_zero_words(uint32_t* p, uint32_t count, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     if (count == 0) return hipSuccess;
     const uint32_t grid = (count + 255) / 256 < 1024 ? (count + 255) / 256 : 1024;
     hipLaunchKernelGGL(zero_words_kernel, dim3(grid), dim3(256), 0, stream, p, count);
@@ -181,6 +184,7 @@ hipError_t launch_zero_words(uint32_t* p, uint32_t count, hipStream_t stream) {
 
 hipError_t launch_extract(const WideSummary& s, uint32_t k, uint64_t N, int kind, uint32_t cap, DevEntry* out,
                           uint32_t* out_count, bool in_lds, unsigned char* scratch, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     const uint32_t bytes = extract_lds_bytes(k);
     if (in_lds) {
         hipFuncSetAttribute((const void*)extract_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -202,6 +206,7 @@ __global__ void reset_kernel(WideSummary s) {
 }
 
 hipError_t launch_reset(const WideSummary& s, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, stream, s);
     return hipGetLastError();
 }

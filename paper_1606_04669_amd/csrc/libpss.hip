@@ -17,6 +17,10 @@
 
 using namespace pss;
 
+namespace pss {
+thread_local int t_last_device_error = 0;
+}  // namespace pss
+
 namespace {
 
 // Device memory the HBM-resident block states of one update may take; the
@@ -156,14 +160,15 @@ int run_blocks(pss_ctx* ctx, const KPlan& p, const uint32_t* d_items, uint64_t n
     const uint32_t k = p.L.k;
     int rc = ctx->blocks.grow(blocks_bytes(chunks, k));
     if (rc != PSS_OK) return rc;
-    unsigned char* gs = nullptr;
-    if (p.L.global_state) {
-        rc = ctx->gstate.grow((size_t)chunks * p.L.state_bytes);
-        if (rc != PSS_OK) return rc;
-        gs = (unsigned char*)ctx->gstate.ptr;
-    }
+    // per-block scratch: the state slabs (state in device memory), then the
+    // error arrays
+    const size_t gbytes = p.L.global_state ? align_up((size_t)chunks * p.L.state_bytes, 256) : 0;
+    rc = ctx->gstate.grow(gbytes + (size_t)chunks * p.L.err_stride * 4);
+    if (rc != PSS_OK) return rc;
+    unsigned char* gs = p.L.global_state ? (unsigned char*)ctx->gstate.ptr : nullptr;
+    uint32_t* errs = (uint32_t*)((unsigned char*)ctx->gstate.ptr + gbytes);
     *out = carve_blocks(ctx->blocks.ptr, chunks, k);
-    return check(launch_chunk_summary(d_items, n, chunks, p.L, *out, gs, st));
+    return check(launch_chunk_summary(d_items, n, chunks, p.L, *out, gs, errs, st));
 }
 
 int ensure_pinned(pss_ctx* ctx, size_t bytes) {
@@ -212,6 +217,10 @@ int pss_phase_times(pss_ctx* ctx, double* ms, uint32_t* launches, int reset) {
     }
     return rc;
 }
+
+int pss_last_device_error(void) { return pss::t_last_device_error; }
+
+const char* pss_device_error_name(int hip_error) { return hipGetErrorName((hipError_t)hip_error); }
 
 const char* pss_strerror(int code) {
     switch (code) {
@@ -293,7 +302,7 @@ uint32_t pss_plan_chunks(const pss_ctx* ctx, uint64_t n, uint32_t k) {
     uint64_t cap_len = n / (16ull * k);
     if (cap_len < 1) cap_len = 1;
     uint64_t c = std::min(want, cap_len);
-    if (L.global_state) c = std::min<uint64_t>(c, kStateBudget / L.state_bytes);
+    if (L.global_state) c = std::min<uint64_t>(c, kStateBudget / (L.state_bytes + 4ull * L.err_stride));
     c = std::min<uint64_t>(c, kMaxChunks);
     return (uint32_t)std::max<uint64_t>(c, 1);
 }
@@ -340,7 +349,7 @@ int pss_update(pss_summary* s, const uint32_t* d_items, uint64_t n, uint32_t chu
         return PSS_OK;
     }
     if (!d_items) return PSS_EINVAL;
-    if (n >= (1ull << 32)) return PSS_ERANGE;
+    if (n >= kStreamBound) return PSS_ERANGE;
     const uint32_t C = chunks ? chunks : pss_plan_chunks(ctx, n, k);
     if (C > kMaxChunks) return PSS_ERANGE;
     DeviceGuard g(ctx->device);
@@ -464,7 +473,7 @@ int pss_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint3
     if (!ctx || (n > 0 && !d_items) || chunks == 0 || (nsel > 0 && (!h_sel || !h_out || !h_sizes || !h_mins)))
         return PSS_EINVAL;
     if (k < 2) return PSS_EINVAL;
-    if (!k_fits(ctx, k) || n >= (1ull << 32) || chunks > kMaxChunks) return PSS_ERANGE;
+    if (!k_fits(ctx, k) || n >= kStreamBound || chunks > kMaxChunks) return PSS_ERANGE;
     for (uint32_t i = 0; i < nsel; ++i)
         if (h_sel[i] >= chunks) return PSS_EINVAL;
     DeviceGuard g(ctx->device);

@@ -51,7 +51,14 @@ struct DeviceGuard {
     }
 };
 
-inline int check(hipError_t e) { return e == hipSuccess ? PSS_OK : PSS_EDEVICE; }
+// The HIP error behind the last PSS_EDEVICE returned on this thread.
+extern thread_local int t_last_device_error;
+
+inline int check(hipError_t e) {
+    if (e == hipSuccess) return PSS_OK;
+    t_last_device_error = (int)e;
+    return PSS_EDEVICE;
+}
 
 struct PhaseMark {
     int phase;
@@ -71,7 +78,7 @@ struct pss_ctx {
     size_t lds_max = 0;          // dynamic LDS per workgroup
     size_t lds_per_cu = 0;
     pss::DeviceBuffer blocks;    // block summaries of one update
-    pss::DeviceBuffer gstate;    // per-block state when it does not fit LDS
+    pss::DeviceBuffer gstate;    // per-block scratch: state slabs (when the state does not fit LDS) and error arrays
     pss::DeviceBuffer cscratch;  // COMBINE level slabs when they do not fit LDS
     pss::DeviceBuffer wscratch;  // fold / merge / report arrays when they do not fit LDS
     pss::DeviceBuffer query;     // report buffer

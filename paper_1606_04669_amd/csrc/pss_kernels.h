@@ -33,9 +33,11 @@ struct DevEntry {
 // Layout of one block summary for k counters: state in LDS when it fits in
 // lds_max bytes (with 16-bit indices), else in a global slab per block.
 ChunkLayout chunk_layout(uint32_t k, size_t lds_max);
-// gstate: chunks * L.state_bytes bytes of device memory when L.global_state.
+// gstate: chunks * L.state_bytes bytes of device memory when L.global_state;
+// errs: chunks * L.err_stride words of device memory (error scratch).
 hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L,
-                                const BlockSummaries& out, unsigned char* gstate, hipStream_t stream);
+                                const BlockSummaries& out, unsigned char* gstate, uint32_t* errs,
+                                hipStream_t stream);
 
 // ---- batched form: many independent streams in one launch sequence ----
 
@@ -45,6 +47,7 @@ struct BatchBlock {
     uint64_t n;             // stream length: bounds every load
     uint64_t begin, end;    // block bounds within the stream (Algorithm 1)
     uint64_t out;           // entry offset of the block summary (capacity k)
+    uint64_t eoff;          // word offset of the block's error scratch (err_stride of its layout)
     uint32_t k;
     uint32_t slots_x16;     // hash slots per counter (x16), result-neutral
 };
@@ -67,10 +70,11 @@ struct BatchReport {
 
 // Persistent launch over nblocks blocks whose k share sort_lanes_per_k;
 // queue: one zeroed counter; waves_per_group waves per workgroup, each with
-// lds_stride bytes of LDS (>= the layout of every block's k and load factor).
+// lds_stride bytes of LDS (>= the layout of every block's k and load factor);
+// errs: base of the blocks' error scratch.
 hipError_t launch_batch_blocks(const BatchBlock* blocks, uint32_t nblocks, uint32_t* queue, uint32_t sort_lanes,
                                uint32_t lds_stride, uint32_t waves_per_group, uint32_t grid,
-                               const BlockSummaries& out, hipStream_t stream);
+                               const BlockSummaries& out, uint32_t* errs, hipStream_t stream);
 // One tree level of a batch (all streams): nodes[0, count), kmax bounds LDS.
 hipError_t launch_batch_combine(const BatchNode* nodes, uint32_t count, uint32_t kmax, const BlockSummaries& base,
                                 hipStream_t stream);

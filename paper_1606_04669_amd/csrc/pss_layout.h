@@ -2,10 +2,10 @@
 // chunk_summary kernel.  One wave owns one layout.  The per-block state (hash
 // table, counts, minimum-level list) lives in LDS when it fits, otherwise in
 // a global-memory slab of state_bytes per block; the input ring and a few
-// small per-window arrays always live in LDS.  A counter's item id is the
-// key of its hash-table entry, and errors are written straight to the
-// block's output array in device memory (read only at the end), which keeps
-// both out of LDS.
+// small per-window arrays always live in LDS.  A counter is a hash-table
+// slot: its entry holds the item id and the count, so there is no separate
+// counter array; errors go to a per-block scratch array in device memory
+// (written at installs, read at the end).
 #pragma once
 
 #include <stdint.h>
@@ -28,19 +28,25 @@ constexpr uint32_t kMaxLdsTableSlots = 65536;
 #define PSS_BUCKET_SLOTS 8
 #endif
 constexpr uint32_t kBucketSlots = PSS_BUCKET_SLOTS;
-// Hash slots per counter x16: 2 per counter up to k = 1024, 1.5 above (a
+// Hash slots per counter x16: 2 per counter up to k = 1024, 1.625 above (a
 // speed / memory trade that never changes results: at k = 2000 the smaller
-// table lets three waves share a CU's LDS instead of two).
+// table lets four waves share a CU's LDS).
 #ifndef PSS_SLOTS_X16
-#define PSS_SLOTS_X16 24
+#define PSS_SLOTS_X16 26
 #endif
 #ifndef PSS_SLOTS_X16_SMALLK
 #define PSS_SLOTS_X16_SMALLK 32
 #endif
 // Overflow slots after the buckets, for items whose two buckets are full.
 constexpr uint32_t kStash = 64;
+// Streams hold fewer than kStreamBound items: a count word of a hash slot
+// keeps its top 128 values for the victims and claims of a window.
+constexpr uint64_t kStreamBound = (1ull << 32) - 128;
 // The level sort's histogram: 257 words.
 constexpr uint32_t kHistBytes = 4 * 257;
+// Register classes (sort registers per lane) from which the level sort's
+// histogram lies over the level list (LDS-resident state).
+constexpr uint32_t kHistOverListMinP = 16;
 
 PSS_HD inline uint32_t next_pow2(uint32_t v) {
     uint32_t p = 1;
@@ -65,13 +71,17 @@ struct ChunkLayout {
     uint32_t k;
     uint32_t nbuckets;      // hash buckets of kBucketSlots slots
     uint32_t tsize;         // kBucketSlots * nbuckets slots (the stash follows them)
+    uint32_t slots;         // tsize + kStash: every slot can hold a counter
     uint32_t global_state;  // 1: state in global memory, 32-bit indices; 0: LDS, 16-bit indices
     // state offsets (bytes from the state base)
-    uint32_t off_table, off_cnt, off_hpos, off_list, off_mark, off_tkey, off_list2, off_tkey2;
+    uint32_t off_table, off_list, off_tkey, off_list2, off_tkey2;
     uint32_t state_bytes;
     // LDS offsets (bytes from the LDS base; the state comes first when it is in LDS)
-    uint32_t off_ring, off_vslot, off_vhpos, off_hist;
+    uint32_t off_ring, off_hist;
     uint32_t lds_bytes;
+    // per-block error scratch in device memory: one uint32 per slot, blocks
+    // err_stride words apart (a multiple of 32: each block starts a cache line)
+    uint32_t err_stride;
 
     // Default hash slots per counter (x16).
     PSS_HD static uint32_t default_slots_x16(uint32_t k) { return k <= 1024 ? PSS_SLOTS_X16_SMALLK : PSS_SLOTS_X16; }
@@ -84,19 +94,23 @@ struct ChunkLayout {
         L.k = k;
         L.global_state = global_state ? 1u : 0u;
         if (slots_per_counter_x16 == 0) slots_per_counter_x16 = default_slots_x16(k);
-        uint32_t slots = (uint32_t)(((uint64_t)k * slots_per_counter_x16 + 15) / 16);
-        if (slots < 256) slots = 256;
-        L.nbuckets = (slots + kBucketSlots - 1) / kBucketSlots;
+        uint32_t want = (uint32_t)(((uint64_t)k * slots_per_counter_x16 + 15) / 16);
+        if (want < 256) want = 256;
+        L.nbuckets = (want + kBucketSlots - 1) / kBucketSlots;
         L.tsize = kBucketSlots * L.nbuckets;
+        L.slots = L.tsize + kStash;
         const uint32_t idx = global_state ? 4u : 2u;
         uint32_t o = 0;
-        L.off_table = o; o = align16(o + 8 * (L.tsize + kStash));  // uint64 entries (key | tag << 32): 64-B buckets, then the stash
-        L.off_cnt = o;   o = align16(o + 4 * k);
-        L.off_hpos = o;  o = align16(o + idx * k);       // table slot of each counter
-        L.off_list = o;  o = align16(o + idx * k);       // counters of the minimum level, by id
-        // uint8 victim ranks; with LDS state also the sort histogram (all marks
-        // are zero while a level is sorted and are cleared again after it)
-        L.off_mark = o;  o = align16(o + (global_state ? k : (k > kHistBytes ? k : kHistBytes)));
+        // the counters: uint64 entries key | count << 32 (count 0: empty; the
+        // top 128 values: victims and claims of a window), 64-B buckets, then
+        // the stash
+        L.off_table = o; o = align16(o + 8 * L.slots);
+        // with LDS state and a large register class the level sort keeps the
+        // list in registers and lays its histogram over it
+        const bool hist_over_list = !global_state && sort_lanes_per_k(k) >= kHistOverListMinP;
+        const uint32_t list_bytes = idx * k;
+        L.off_list = o;                                  // slots of the minimum level, by id
+        o = align16(o + (hist_over_list && list_bytes < kHistBytes ? kHistBytes : list_bytes));
         L.off_tkey = o;  o = align16(o + 4 * k);         // ids while a level is sorted
         L.off_list2 = o;
         L.off_tkey2 = o;
@@ -107,15 +121,18 @@ struct ChunkLayout {
         L.state_bytes = o;
         uint32_t l = global_state ? 0u : o;
         L.off_ring = l;  l = align16(l + 4 * kRing);     // staged input items
-        L.off_vslot = l; l = align16(l + 4 * 64);        // victim counter per rank
-        L.off_vhpos = l; l = align16(l + 4 * 64);        // its table slot
-        L.off_hist = global_state ? l : L.off_mark;      // bucket counts / starts while a level is sorted
-        if (global_state) l = align16(l + kHistBytes);
+        // bucket counts / starts while a level is sorted
+        if (hist_over_list) {
+            L.off_hist = L.off_list;
+        } else {
+            L.off_hist = l;  l = align16(l + kHistBytes);
+        }
         L.lds_bytes = l;
+        L.err_stride = (L.slots + 31u) & ~31u;
         return L;
     }
 
-    PSS_HD bool fits_lds_indices() const { return tsize + kStash <= kMaxLdsTableSlots && k <= 65535u; }
+    PSS_HD bool fits_lds_indices() const { return slots <= kMaxLdsTableSlots && k <= 65535u; }
 };
 
 }  // namespace pss

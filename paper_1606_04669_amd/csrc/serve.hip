@@ -154,10 +154,10 @@ struct pss_server {
 namespace {
 
 // Device bytes a launch needs for an append of n items with k counters and
-// C blocks: the staged items plus the block summaries.
+// C blocks: the staged items, the block summaries and their error scratch.
 size_t append_bytes(uint64_t n, uint32_t k, uint32_t C) {
     return align_up(n * 4, 16) + (size_t)C * k * 12 + (size_t)C * 8 + (size_t)C * sizeof(BatchBlock) +
-           (size_t)C * sizeof(BatchNode) + sizeof(ServeFold);
+           (size_t)C * sizeof(BatchNode) + sizeof(ServeFold) + (size_t)C * 4 * ChunkLayout::make(k, false).err_stride;
 }
 
 // Copies every append's items into the pinned staging buffer; large launches
@@ -230,6 +230,7 @@ int run_launch(pss_server* srv, uint32_t si) {
             h.d.begin = (uint64_t)c * q->n / q->chunks;  // Algorithm 1's block bounds
             h.d.end = (uint64_t)(c + 1) * q->n / q->chunks;
             h.d.out = 0;
+            h.d.eoff = 0;
             h.d.k = k;
             h.d.slots_x16 = ChunkLayout::default_slots_x16(k);
             h.cls = class_of(k);
@@ -255,10 +256,12 @@ int run_launch(pss_server* srv, uint32_t si) {
         }
     }
     std::vector<uint32_t> where(nb);
-    uint64_t entries = 0;
+    uint64_t entries = 0, ewords = 0;
     for (uint32_t i = 0; i < nb; ++i) {
         hb[i].d.out = entries;
         entries += hb[i].d.k;
+        hb[i].d.eoff = ewords;
+        ewords += ChunkLayout::make(hb[i].d.k, false, hb[i].d.slots_x16).err_stride;
         where[first_blk[hb[i].req] + hb[i].c] = i;
     }
     // tree levels over every append, then the folds
@@ -326,7 +329,8 @@ int run_launch(pss_server* srv, uint32_t si) {
     sl.nquery = (uint32_t)queries.size();
 
     // device layout: items | block summaries (item, cnt, err, size, min) |
-    // descriptors (blocks, nodes, folds, queries, queues) | query output (entries, counts)
+    // descriptors (blocks, nodes, folds, queries, queues) | query output
+    // (entries, counts) | error scratch of the blocks
     const size_t it_b = align_up(items_total * 4, 256);
     const size_t e4 = align_up(entries * 4, 256);
     const size_t h4 = align_up((size_t)nb * 4, 256);
@@ -344,7 +348,8 @@ int run_launch(pss_server* srv, uint32_t si) {
     const size_t off_queue = sl.off_desc + sl.desc_bytes;
     sl.off_out = off_queue + qq;
     sl.out_bytes = ob + cb;
-    const size_t total = sl.off_out + sl.out_bytes;
+    const size_t off_errs = sl.off_out + sl.out_bytes;
+    const size_t total = off_errs + align_up(ewords * 4, 256);
     int rc = sl.dev.grow(total);
     if (rc != PSS_OK) return rc;
     // host staging: items then descriptors, contiguous as on the device
@@ -382,6 +387,7 @@ int run_launch(pss_server* srv, uint32_t si) {
     uint32_t* d_queue = (uint32_t*)(dbase + off_queue);
     DevEntry* d_out = (DevEntry*)(dbase + sl.off_out);
     uint32_t* d_counts = (uint32_t*)(dbase + sl.off_out + ob);
+    uint32_t* d_errs = (uint32_t*)(dbase + off_errs);
 
     rc = check(launch_zero_words(d_queue, kSrvClasses, st));
     for (uint32_t i = 0; rc == PSS_OK && i < nb;) {
@@ -397,7 +403,7 @@ int run_launch(pss_server* srv, uint32_t si) {
         rc = check(launch_batch_blocks(d_blocks + first, count, d_queue + cls, 2u << cls, stride, 1, grid,
                                        BlockSummaries{sums.item, sums.cnt, sums.err, sums.size + first,
                                                       sums.min + first},
-                                       st));
+                                       d_errs, st));
     }
     for (size_t l = 0; rc == PSS_OK && l < lvl_first.size(); ++l)
         rc = check(launch_batch_combine(d_nodes + lvl_first[l], lvl_count[l], lvl_kmax[l], sums, st));
@@ -702,7 +708,7 @@ void pss_server_destroy(pss_server* srv) {
 int pss_server_append(pss_server* srv, uint32_t sid, const uint32_t* h_items, uint64_t n, uint32_t chunks,
                       uint64_t* ticket) {
     if (!srv || !ticket || sid >= srv->nsum || (n > 0 && !h_items)) return PSS_EINVAL;
-    if (n >= (1ull << 32) || chunks > kMaxChunks) return PSS_ERANGE;
+    if (n >= kStreamBound || chunks > kMaxChunks) return PSS_ERANGE;
     const uint32_t k = srv->ks[sid];
     const uint32_t C = n == 0 ? 0 : (chunks ? chunks : append_chunks(n, k, srv->opts.block_len));
     if (n && append_bytes(n, k, C) > srv->slot_budget) return PSS_ERANGE;  // can never be admitted

@@ -28,7 +28,7 @@ def lib():
 def test_header_declares_the_boundary():
     fns = declared_functions()
     for f in ["pss_ctx_create", "pss_ctx_destroy", "pss_create", "pss_destroy", "pss_update", "pss_merge",
-              "pss_query", "pss_run", "pss_strerror", "pss_block_summaries", "pss_plan_chunks", "pss_max_k",
+              "pss_query", "pss_run", "pss_strerror", "pss_last_device_error", "pss_device_error_name", "pss_block_summaries", "pss_plan_chunks", "pss_max_k",
               "pss_batch_create", "pss_batch_run", "pss_batch_destroy", "pss_run_batched"]:
         assert f in fns
 
@@ -46,6 +46,7 @@ def test_strerror_and_null_handling_without_gpu(lib):
     assert lib.pss_strerror(0) == b"ok"
     assert lib.pss_strerror(-5) == b"output buffer too small"
     assert lib.pss_strerror(12345) == b"unknown error"
+    assert lib.pss_last_device_error() == 0  # nothing failed on this thread
     # null handles are rejected before any device call
     lib.pss_ctx_create.argtypes = [ctypes.c_int, ctypes.c_void_p]
     assert lib.pss_ctx_create(0, None) == -1

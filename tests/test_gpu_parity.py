@@ -161,6 +161,23 @@ def test_uniform_and_adversarial_medium(B, ctx):
     assert W.adversarial_planted_id(4, d=1 << 14) in [int(e["item"]) for e in want]
 
 
+def test_skewed_ids_level_sort_fallback(B, ctx):
+    # levels whose ids share all bits but the top one and the low 12: the
+    # digit sort finds an oversized bucket and the level is sorted by the
+    # fallback network (state in LDS, k in two register classes)
+    a = W.skewed_ids(1 << 18, seed=5)
+    for k, C in ((700, 4), (1500, 2)):
+        say("skewed ids n=2^18 k=%d C=%d" % (k, C))
+        got = B.pss_block_summaries(ctx, dev(a), k, C, list(range(C)))
+        ref = O.chunk_summaries(a, k, C)
+        for c in range(C):
+            ent, mn = got[c]
+            assert sorted(B.to_tuples(ent)) == sorted(O.to_tuples(ref[c].entries)), (k, c)
+            assert mn == ref[c].m, (k, c)
+        run, _ = B.pss_run(ctx, dev(a), k=k, chunks=C)
+        assert B.to_tuples(run) == O.to_tuples(O.run(a, k, C)), k
+
+
 def test_errors_and_truncation(B, ctx):
     items = dev([1, 2, 3, 1, 1, 1, 2, 2])
     with pytest.raises(B.PssError) as e:

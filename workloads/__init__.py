@@ -129,6 +129,17 @@ def adversarial(n: int, seed: int, d: int = 1 << 20, threads: int | None = None,
     return out
 
 
+def skewed_ids(n: int, seed: int, low_bits: int = 12, high_share: float = 0.01) -> np.ndarray:
+    """Ids below 2^low_bits, a high_share of them with bit 31 set: the ids
+    of a level then differ in bit 31 while most share every bit above
+    low_bits (a structure that defeats digit bucketing on the top bits)."""
+    u = uniform(n, seed)
+    flag = uniform(n, seed + 7919)
+    out = u & np.uint32((1 << low_bits) - 1)
+    out[flag < np.uint32(int(high_share * 2.0 ** 32))] |= np.uint32(1 << 31)
+    return out
+
+
 def adversarial_planted_id(seed: int, d: int = 1 << 20) -> int:
     return fmix32(d ^ (subkey(seed, 3) & 0xFFFFFFFF))
 

@@ -343,7 +343,20 @@ __device__ bool sort_level_buckets(uint16_t* list, const ID& ids, uint32_t* tkey
             const uint32_t d = sd[j] >> 16;
             const uint32_t b0 = hist[d], b1 = hist[d + 1];
             uint32_t r = 0;
-            for (uint32_t t = b0; t < b1; ++t) r += tkey[t] < id[j] ? 1u : 0u;
+            if constexpr (OVER) {
+                // four ids per step, their loads in flight together (addresses
+                // past the bucket's end are clamped to its first entry)
+                for (uint32_t t = b0; t < b1; t += 4) {
+                    const uint32_t k0 = tkey[t];
+                    const uint32_t k1 = tkey[t + 1 < b1 ? t + 1 : b0];
+                    const uint32_t k2 = tkey[t + 2 < b1 ? t + 2 : b0];
+                    const uint32_t k3 = tkey[t + 3 < b1 ? t + 3 : b0];
+                    r += (k0 < id[j] ? 1u : 0u) + ((t + 1 < b1 && k1 < id[j]) ? 1u : 0u) +
+                         ((t + 2 < b1 && k2 < id[j]) ? 1u : 0u) + ((t + 3 < b1 && k3 < id[j]) ? 1u : 0u);
+                }
+            } else {
+                for (uint32_t t = b0; t < b1; ++t) r += tkey[t] < id[j] ? 1u : 0u;
+            }
             pin[j] = b0 + r;
         }
     }
@@ -707,6 +720,9 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
     KSTAT_DECL
     const unsigned long long t_start = KSTAT_NOW();
     uint64_t pos = begin;
+    // each window's items are read from the ring at the end of the window
+    // before (the refill at the top never overwrites them)
+    uint32_t xn = ring[(uint32_t)(pos + lane) & (kRing - 1)];
     while (pos < end && !failed) {
         KSTAT_ADD(0, 1);
         if (pos >= rbase + kRingHalf) {
@@ -755,7 +771,7 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
 
         const uint32_t wl = (uint32_t)((end - pos) < kWave ? (end - pos) : kWave);
         const bool valid = lane < wl;
-        const uint32_t x = valid ? ring[(uint32_t)(pos + lane) & (kRing - 1)] : 0u;
+        const uint32_t x = valid ? xn : 0u;
 
         // victims for this window (list entries list_ptr + lane), fetched early
         // when the last window needed them.  The loads are unconditional on
@@ -801,8 +817,9 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         KSTAT_ADD(15, KSTAT_NOW() - tw);
         if (missmask == 0) {
             // all hits: increments commute
-            if (hit) atomicAdd(&words[2 * slot + 1], 1u);
             pos += wl;
+            xn = ring[(uint32_t)(pos + lane) & (kRing - 1)];
+            if (hit) atomicAdd(&words[2 * slot + 1], 1u);
             last_slow = 0;
             KSTAT_ADD(1, 1);
             KSTAT_ADD(2, KSTAT_NOW() - tw);
@@ -1019,6 +1036,7 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
             list_ptr = uniform(list_ptr + (uint32_t)__builtin_ctzll(lastm) + 1u);
         }
         pos += p;
+        xn = ring[(uint32_t)(pos + lane) & (kRing - 1)];
         wave_sync();
         KSTAT_ADD(3, KSTAT_NOW() - tw);
         KSTAT_ADD(11, p < wl ? 1 : 0);

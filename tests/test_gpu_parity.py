@@ -202,6 +202,13 @@ def test_errors_and_truncation(B, ctx):
     with pytest.raises(B.PssError) as e:
         B.pss_merge(a, a)
     assert e.value.code == B.PSS_EINVAL
+    # stream lengths reach 2^32 - 128 at most (the top count values are the
+    # kernel's window tags); the bound is checked before any device work
+    for n in ((1 << 32) - 128, 1 << 32):
+        with pytest.raises(B.PssError) as e:
+            B.pss_update(a, items, chunks=1, n=n)
+        assert e.value.code == B.PSS_ERANGE, n
+    assert B.last_device_error()[0] == 0
 
 
 def test_update_merge_query_sequence(B, ctx):

@@ -1,0 +1,129 @@
+"""Host checks of the block layout (the header shared by the host launcher
+and the block kernel), compiled with the host C++ compiler: no GPU needed.
+
+The layout decides what fits in a CU's LDS and where the level sort's
+histogram lies; the kernel relies on these properties.
+"""
+import json
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1606_04669_amd", "csrc")
+
+PROGRAM = r"""
+#include <cstdio>
+#include <initializer_list>
+#include "pss_layout.h"
+using namespace pss;
+int main() {
+    printf("[");
+    bool first = true;
+    auto emit = [&](unsigned k, unsigned g) {
+        for (unsigned sx : {0u, 32u, 48u, 64u}) {
+            ChunkLayout L = ChunkLayout::make(k, g != 0, sx);
+            printf("%s{\"k\":%u,\"g\":%u,\"sx\":%u,\"nb\":%u,\"ts\":%u,\"slots\":%u,\"table\":%u,\"list\":%u,"
+                   "\"tkey\":%u,\"list2\":%u,\"tkey2\":%u,\"state\":%u,\"ring\":%u,\"hist\":%u,\"lds\":%u,"
+                   "\"es\":%u,\"lanes\":%u}",
+                   first ? "" : ",", k, g, sx, L.nbuckets, L.tsize, L.slots, L.off_table, L.off_list, L.off_tkey,
+                   L.off_list2, L.off_tkey2, L.state_bytes, L.off_ring, L.off_hist, L.lds_bytes, L.err_stride,
+                   sort_lanes_per_k(k));
+            first = false;
+        }
+    };
+    for (unsigned g = 0; g < 2; ++g) {
+        for (unsigned k = 2; k <= 70000; k = k < 600 ? k + 1 : k + 37)
+            if (g || k <= 8192) emit(k, g);
+        for (unsigned k : {1000u, 1024u, 1025u, 2000u, 2048u, 4096u, 10000u, 50000u})
+            if (g || k <= 8192) emit(k, g);
+    }
+    printf("]\n");
+    printf("%u %u %u %u %llu\n", kBucketSlots, kStash, kHistBytes, kHistOverListMinP, (unsigned long long)kStreamBound);
+    return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def layouts(tmp_path_factory):
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if not cxx:
+        pytest.skip("no host C++ compiler")
+    d = tmp_path_factory.mktemp("layout")
+    src = d / "layout.cpp"
+    src.write_text(PROGRAM)
+    exe = d / "layout"
+    cc = subprocess.run([cxx, "-std=c++17", "-O1", "-I", CSRC, str(src), "-o", str(exe)], capture_output=True,
+                        text=True)
+    assert cc.returncode == 0, cc.stderr
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines()
+    consts = [int(v) for v in out[1].split()]
+    return json.loads(out[0]), dict(zip(["bucket", "stash", "hist", "over_min", "bound"], consts))
+
+
+def test_regions_are_disjoint_and_sized(layouts):
+    rows, c = layouts
+    for r in rows:
+        k, slots = r["k"], r["slots"]
+        idx = 4 if r["g"] else 2
+        assert r["ts"] == c["bucket"] * r["nb"] and slots == r["ts"] + c["stash"]
+        assert slots >= k + 64  # every counter plus a full window of claims has a slot
+        assert r["nb"] >= 2  # two distinct buckets per item
+        assert r["table"] == 0
+        assert r["list"] >= 8 * slots
+        assert r["tkey"] >= r["list"] + idx * k
+        assert r["state"] >= r["tkey"] + 4 * k
+        if r["g"]:
+            assert r["list2"] >= r["tkey"] + 4 * k and r["tkey2"] >= r["list2"] + 4 * k
+            assert r["state"] >= r["tkey2"] + 4 * k
+            assert r["ring"] == 0  # LDS holds only the ring and the histogram
+        else:
+            assert r["ring"] >= r["state"]
+        assert r["lds"] >= r["ring"] + 4 * 512
+        for off in ("list", "tkey", "state", "ring", "hist", "lds"):
+            assert r[off] % 16 == 0, (off, r)
+        assert r["es"] % 32 == 0 and r["es"] >= slots
+
+
+def test_histogram_over_the_list_only_where_the_sort_keeps_it_in_registers(layouts):
+    rows, c = layouts
+    for r in rows:
+        over = not r["g"] and r["lanes"] >= c["over_min"]
+        if over:
+            assert r["hist"] == r["list"]
+            assert r["tkey"] - r["list"] >= c["hist"]  # the list region holds the histogram
+        else:
+            assert r["hist"] >= r["ring"] + 4 * 512 and r["lds"] >= r["hist"] + c["hist"]
+
+
+def test_footprint_grows_with_k_inside_a_class(layouts):
+    # a batched launch sizes every wave's LDS slab by the largest k of its class
+    rows, _ = layouts
+    by = {}
+    for r in rows:
+        if not r["g"]:
+            by.setdefault((r["sx"], r["lanes"]), []).append((r["k"], r["lds"]))
+    for v in by.values():
+        v.sort()
+        assert all(a[1] <= b[1] for a, b in zip(v, v[1:]))
+
+
+def test_benchmark_sizes_fit_their_wave_counts(layouts):
+    # LDS is allocated per workgroup in 512-byte granules out of 160 KiB
+    rows, _ = layouts
+    lds = {(r["k"], r["sx"]): r["lds"] for r in rows if not r["g"]}
+
+    def waves(b):
+        return (160 * 1024) // (-(-b // 512) * 512)
+
+    assert waves(lds[(500, 0)]) >= 11
+    assert waves(lds[(2000, 0)]) >= 4
+
+
+def test_stream_bound_leaves_room_for_the_window_tags(layouts):
+    _, c = layouts
+    # two tag ranges of 64 values (victim ranks, claiming lanes) above every count
+    assert c["bound"] == (1 << 32) - 128

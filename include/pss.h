@@ -104,7 +104,7 @@ int pss_create(pss_ctx* ctx, uint32_t k, pss_summary** out);
  * accepted. */
 void pss_destroy(pss_summary* s);
 
-/* Append n items (device array d_items, n < 2^32 - 64) to summary s:
+/* Append n items (device array d_items, n < 2^32 - 128) to summary s:
  *   B = fixed-tree COMBINE of the Space Saving summaries of C blocks of
  *       d_items (Algorithm 1 up to the reduction), then S <- COMBINE(S, B)
  *       and N <- N + n.
@@ -128,7 +128,7 @@ int pss_query(const pss_summary* s, int kind, pss_entry* h_out, uint32_t cap, ui
 /* ParallelSpaceSaving(A, n, C, k) (Algorithm 1) in one call: the k-majority
  * candidates of the device array d_items[0, n), written to h_out (cap
  * entries) in canonical order, *n_out = number reported.  Requires
- * 2 <= k <= n (PSS_ERANGE otherwise).  chunks = 0 picks C; *chunks_used (may
+ * 2 <= k <= n < 2^32 - 128 (PSS_ERANGE otherwise).  chunks = 0 picks C; *chunks_used (may
  * be NULL) receives it.  Blocks until the result is on the host. */
 int pss_run(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks,
             pss_entry* h_out, uint32_t cap, uint32_t* n_out, uint32_t* chunks_used, void* stream);
@@ -137,7 +137,8 @@ int pss_run(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint3
  * for C = chunks blocks (same kernel launch as pss_update) and copies the
  * summaries of the nsel blocks listed in h_sel to the host: block h_sel[i]
  * goes to h_out[i*k ...] (unordered entries), its size to h_sizes[i] and its
- * minimum (0 when not full) to h_mins[i].  Blocks until done. */
+ * minimum (0 when not full) to h_mins[i].  PSS_ERANGE for n >= 2^32 - 128.
+ * Blocks until done. */
 int pss_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks,
                         const uint32_t* h_sel, uint32_t nsel, pss_entry* h_out, uint32_t* h_sizes,
                         uint64_t* h_mins, void* stream);
@@ -147,7 +148,7 @@ int pss_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint3
  * Stream s is the device array h_items[s][0, h_lens[s]) with k = h_ks[s]
  * counters; its result is exactly that of pss_run on it with
  * C = h_chunks[s] (Algorithm 1 with Algorithm 2 as the reduction): the batch
- * changes scheduling only.  Requires 2 <= k_s <= n_s, n_s < 2^32 - 64 and
+ * changes scheduling only.  Requires 2 <= k_s <= n_s, n_s < 2^32 - 128 and
  * k_s <= pss_batch_max_k() (PSS_ERANGE otherwise). */
 typedef struct pss_batch pss_batch;
 
@@ -247,7 +248,7 @@ void pss_server_destroy(pss_server* srv);
 /* Submit an append of h_items[0, n) (host memory, caller-owned, valid until
  * the ticket completes) to summary sid with C = chunks blocks (0: chosen from
  * opts.block_len, reported by pss_server_wait).  Returns at once with
- * *ticket.  PSS_ERANGE if n >= 2^32 - 64 or the append can never fit the budget. */
+ * *ticket.  PSS_ERANGE if n >= 2^32 - 128 or the append can never fit the budget. */
 int pss_server_append(pss_server* srv, uint32_t sid, const uint32_t* h_items, uint64_t n, uint32_t chunks,
                       uint64_t* ticket);
 

@@ -51,3 +51,11 @@ def test_adversarial_stream_structure():
     rest = np.delete(a, np.arange(19, n, 20))
     assert planted not in set(rest.tolist())
     assert len(np.unique(rest)) == 1 << 10
+
+
+def test_skewed_ids_structure():
+    a = W.skewed_ids(200_000, seed=5)
+    assert np.array_equal(a, W.skewed_ids(200_000, seed=5))
+    high = (a >> 31) == 1
+    assert 0.008 < high.mean() < 0.012  # about 1% carry bit 31
+    assert np.all((a & np.uint32(0x7FFFFFFF)) < (1 << 12))  # every other bit above the low 12 is clear

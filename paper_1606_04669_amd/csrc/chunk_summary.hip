@@ -76,16 +76,39 @@ __device__ __forceinline__ uint64_t make_entry(uint32_t key, uint32_t tag) {
     return ((uint64_t)tag << 32) | key;
 }
 
-// The two buckets of an item: multiplicative hashes scaled to nb buckets;
-// the second is moved to the neighbour of the first when they coincide.
-__device__ __forceinline__ uint32_t home_bucket(uint32_t x, uint32_t nb) {
-    return (uint32_t)(((uint64_t)(x * 0x9E3779B1u) * nb) >> 32);
+// The hash functions of one attempt at a block.  The table only indexes the
+// counters, so every choice of multipliers gives the same summary; the first
+// attempt uses fixed ones, and a block whose items overflow a bucket pair
+// and the stash under them (possible for ids chosen to collide) is run again
+// from its start with other odd multipliers (SplitMix64 of the attempt).
+struct HashKeys {
+    uint32_t h1, h2, h3, pick;
+};
+
+constexpr uint32_t kHashAttempts = 4;
+
+__device__ __forceinline__ HashKeys hash_keys(uint32_t attempt) {
+    if (attempt == 0) return HashKeys{0x9E3779B1u, 0x85EBCA77u, 0xC2B2AE3Du, 0x2C1B3C6Du};
+    uint64_t z = (uint64_t)attempt * 0x9E3779B97F4A7C15ull;
+    uint64_t a = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    a = (a ^ (a >> 27)) * 0x94D049BB133111EBull;
+    a ^= a >> 31;
+    uint64_t b = (a + 0x9E3779B97F4A7C15ull) * 0xBF58476D1CE4E5B9ull;
+    b = (b ^ (b >> 27)) * 0x94D049BB133111EBull;
+    b ^= b >> 31;
+    return HashKeys{(uint32_t)a | 1u, (uint32_t)(a >> 32) | 1u, (uint32_t)b | 1u, (uint32_t)(b >> 32) | 1u};
 }
 
-__device__ __forceinline__ uint32_t alt_bucket(uint32_t x, uint32_t nb, uint32_t b1) {
-    uint32_t h = x * 0x85EBCA77u;
+// The two buckets of an item: multiplicative hashes scaled to nb buckets;
+// the second is moved to the neighbour of the first when they coincide.
+__device__ __forceinline__ uint32_t home_bucket(uint32_t x, uint32_t nb, const HashKeys& hk) {
+    return (uint32_t)(((uint64_t)(x * hk.h1) * nb) >> 32);
+}
+
+__device__ __forceinline__ uint32_t alt_bucket(uint32_t x, uint32_t nb, uint32_t b1, const HashKeys& hk) {
+    uint32_t h = x * hk.h2;
     h = (h << 15) | (h >> 17);
-    const uint32_t b2 = (uint32_t)(((uint64_t)(h * 0xC2B2AE3Du) * nb) >> 32);
+    const uint32_t b2 = (uint32_t)(((uint64_t)(h * hk.h3) * nb) >> 32);
     return b2 != b1 ? b2 : (b1 + 1 == nb ? 0u : b1 + 1);
 }
 
@@ -130,9 +153,9 @@ __device__ __forceinline__ uint32_t empty_mask(const Bucket& B) {
 // the (h mod popcount(e))-th free slot for a hash h of the item, so that
 // equal items pick the same slot and different items spread over the free
 // ones.
-__device__ __forceinline__ uint32_t pick_free(uint32_t e, uint32_t x) {
+__device__ __forceinline__ uint32_t pick_free(uint32_t e, uint32_t x, uint32_t mult) {
     const uint32_t n = (uint32_t)__builtin_popcount(e);
-    uint32_t r = (((x * 0x2C1B3C6Du) >> 16) * n) >> 16;  // in [0, n)
+    uint32_t r = (((x * mult) >> 16) * n) >> 16;  // in [0, n)
     for (uint32_t i = 0; i < kBucketSlots; ++i) {  // drop the r lowest set bits
         const bool go = i < r;
         e = go ? (e & (e - 1u)) : e;
@@ -672,14 +695,17 @@ __device__ __forceinline__ void store_half(uint32_t* ring, uint64_t tile, const 
 // state does not fit LDS), else sb is in LDS.  lds holds the input ring and
 // the per-window arrays; errs is the block's error scratch (one word per
 // slot).  Writes entries [0, size) to o_item/o_cnt/o_err and the header to
-// *o_size, *o_min.
+// *o_size, *o_min.  Returns kOverflow, with nothing written, when a new
+// item found no free slot under the hash functions hk (the caller runs the
+// block again with other ones); else kDone.
+constexpr uint32_t kDone = 0, kOverflow = 1;
 template <int P, bool G>
-__device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ items, uint64_t n, uint64_t begin,
-                                                uint64_t end, const ChunkLayout& L, int vec_ok, unsigned char* sb,
-                                                unsigned char* lds, uint32_t* __restrict__ errs,
-                                                uint32_t* __restrict__ o_item, uint32_t* __restrict__ o_cnt,
-                                                uint32_t* __restrict__ o_err, uint32_t* __restrict__ o_size,
-                                                uint32_t* __restrict__ o_min) {
+__device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__ items, uint64_t n, uint64_t begin,
+                                                    uint64_t end, const ChunkLayout& L, int vec_ok, unsigned char* sb,
+                                                    unsigned char* lds, uint32_t* __restrict__ errs,
+                                                    uint32_t* __restrict__ o_item, uint32_t* __restrict__ o_cnt,
+                                                    uint32_t* __restrict__ o_err, uint32_t* __restrict__ o_size,
+                                                    uint32_t* __restrict__ o_min, const HashKeys hk) {
     using idx_t = typename std::conditional<G, uint32_t, uint16_t>::type;
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t k = L.k;
@@ -749,7 +775,7 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
             // listed as a victim by slot.
             const bool cand = slive && (!full || c != m);
             if (ballot(cand)) {
-                const uint32_t s1 = home_bucket(skey, NB), s2 = alt_bucket(skey, NB, s1);
+                const uint32_t s1 = home_bucket(skey, NB, hk), s2 = alt_bucket(skey, NB, s1, hk);
                 const Bucket B1 = load_bucket(tbl4, s1), B2 = load_bucket(tbl4, s2);
                 const uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2);
                 bool moved = false;
@@ -791,10 +817,10 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
 
         // 1. look up against the state at window start: the item's two buckets
         //    (eight 16-byte loads, branch-free), then the stash while it is used
-        bool hit = false, miss = false, bad = false;
+        bool hit = false, miss = false, bad = false, nofree = false;
         uint32_t slot = 0, hp = kNone;
-        const uint32_t b1 = home_bucket(x, NB);
-        const uint32_t b2 = alt_bucket(x, NB, b1);
+        const uint32_t b1 = home_bucket(x, NB, hk);
+        const uint32_t b2 = alt_bucket(x, NB, b1, hk);
         Bucket B1 = load_bucket(tbl4, b1), B2 = load_bucket(tbl4, b2);
         {
             const uint32_t h1 = match_mask(B1, x), h2 = match_mask(B2, x);
@@ -848,8 +874,8 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                 uint32_t h = kNone;
                 bool join = false;
                 if (e1 | e2) {
-                    h = __builtin_popcount(e1) >= __builtin_popcount(e2) ? kBucketSlots * b1 + pick_free(e1, x)
-                                                                         : kBucketSlots * b2 + pick_free(e2, x);
+                    h = __builtin_popcount(e1) >= __builtin_popcount(e2) ? kBucketSlots * b1 + pick_free(e1, x, hk.pick)
+                                                                         : kBucketSlots * b2 + pick_free(e2, x, hk.pick);
                 } else {
                     // both buckets full: the value's claim, or a free slot, in the stash
                     uint32_t fe = kNone;
@@ -868,8 +894,9 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
                     }
                     if (!join) h = fe;
                 }
-                if (h == kNone) {  // no free slot anywhere
+                if (h == kNone) {  // no free slot in the item's buckets or the stash
                     bad = true;
+                    nofree = true;
                     break;
                 }
                 if (!join) {
@@ -897,7 +924,7 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
             }
         }
         if (ballot(bad)) {
-            failed = 1;
+            failed = ballot(nofree) ? 2u : 1u;  // 2: the hash functions, not the algorithm
             continue;
         }
         KSTAT_ADD(17, popc64(ballot(miss && hp >= T)));
@@ -1048,12 +1075,13 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
     // write the summary, compacted from the slots, and its minimum (0 while
     // fewer than k counters are used)
     wave_sync();
+    if (failed == 2) return kOverflow;
     if (failed) {
         if (lane == 0) {
             *o_size = kBlockFailed;
             *o_min = 0;
         }
-        return;
+        return kDone;
     }
     uint32_t mn = 0xFFFFFFFFu, outn = 0;
     for (uint32_t b = 0; b < S; b += kWave) {
@@ -1076,6 +1104,28 @@ __device__ __forceinline__ void summarize_block(const uint32_t* __restrict__ ite
         *o_size = outn == size ? size : kBlockFailed;  // the slots hold exactly the counters
         *o_min = mo;
     }
+    return kDone;
+}
+
+// A block under the attempts' hash functions in turn; after the last one
+// overflows, the block is marked failed (the caller sees a device error).
+template <int P, bool G>
+__device__ __forceinline__ void summarize_block_any(const uint32_t* __restrict__ items, uint64_t n, uint64_t begin,
+                                                    uint64_t end, const ChunkLayout& L, int vec_ok,
+                                                    unsigned char* sb, unsigned char* lds,
+                                                    uint32_t* __restrict__ errs, uint32_t* __restrict__ o_item,
+                                                    uint32_t* __restrict__ o_cnt, uint32_t* __restrict__ o_err,
+                                                    uint32_t* __restrict__ o_size, uint32_t* __restrict__ o_min) {
+    for (uint32_t attempt = 0; attempt < kHashAttempts; ++attempt) {
+        if (summarize_block<P, G>(items, n, begin, end, L, vec_ok, sb, lds, errs, o_item, o_cnt, o_err, o_size, o_min,
+                                  hash_keys(attempt)) == kDone)
+            return;
+        wave_sync();  // the next attempt clears the table this one used
+    }
+    if (lane_id() == 0) {
+        *o_size = kBlockFailed;
+        *o_min = 0;
+    }
 }
 
 // One wave per block c of C: [floor(c n / C), floor((c+1) n / C)) (Algorithm
@@ -1097,7 +1147,7 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
     const uint64_t begin = (uint64_t)c * n / chunks;
     const uint64_t end = (uint64_t)(c + 1) * n / chunks;
     const uint64_t ob = (uint64_t)c * L.k;
-    summarize_block<P, G>(items, n, begin, end, L, vec_ok, sb, smem, errs + (size_t)c * L.err_stride, o_item + ob,
+    summarize_block_any<P, G>(items, n, begin, end, L, vec_ok, sb, smem, errs + (size_t)c * L.err_stride, o_item + ob,
                           o_cnt + ob, o_err + ob, o_size + c, o_min + c);
 }
 
@@ -1127,7 +1177,7 @@ __global__ __launch_bounds__(64 * W) void batch_blocks_kernel(const BatchBlock* 
         const BatchBlock bb = blocks[b];
         const ChunkLayout L = ChunkLayout::make(bb.k, false, bb.slots_x16);
         const int vec_ok = ((uintptr_t)bb.items & 15u) == 0;
-        summarize_block<P, false>(bb.items, bb.n, bb.begin, bb.end, L, vec_ok, lds, lds, errs + bb.eoff,
+        summarize_block_any<P, false>(bb.items, bb.n, bb.begin, bb.end, L, vec_ok, lds, lds, errs + bb.eoff,
                                   o_item + bb.out, o_cnt + bb.out, o_err + bb.out, o_size + b, o_min + b);
         wave_sync();  // the slab is reused by the next block
     }

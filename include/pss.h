@@ -35,6 +35,11 @@
  *
  * Errors: every int-returning function returns PSS_OK (0) or a negative
  * PSS_E* code and never throws.  A failed call leaves summaries unchanged.
+ * Updates and merges are all or nothing also when the failure is found on
+ * the device after the call has returned (a block whose internal invariant
+ * check fails): the summary's entries and its N stay as they were, and the
+ * next pss_query on it returns PSS_EDEVICE once (later queries see the
+ * unchanged summary).
  * Handles are not thread-safe: serialise calls on one summary or context.
  * A context's workspace (block summaries, scratch) is shared by the calls
  * made with it: queue them on one stream, or synchronise between calls made
@@ -92,6 +97,13 @@ int pss_ctx_create(int device, pss_ctx** out);
  * destroyed first.  NULL is accepted. */
 void pss_ctx_destroy(pss_ctx* ctx);
 
+/* Limit the device memory the context's workspaces (block summaries, block
+ * scratch, COMBINE and report scratch) may hold in all to `bytes` (0 = no
+ * limit).  A call that would grow them beyond it returns PSS_ENOMEM before
+ * queueing any work, so summaries are left unchanged.  Workspace already
+ * held is kept.  Returns PSS_EINVAL for a null ctx. */
+int pss_ctx_set_budget(pss_ctx* ctx, uint64_t bytes);
+
 /* Chunk count the library picks for n items and k counters when a call is
  * given chunks = 0 (a deterministic function of n, k and the device). */
 uint32_t pss_plan_chunks(const pss_ctx* ctx, uint64_t n, uint32_t k);
@@ -114,14 +126,18 @@ int pss_update(pss_summary* s, const uint32_t* d_items, uint64_t n, uint32_t chu
                uint32_t* chunks_used);
 
 /* dst <- COMBINE(dst, src) (Algorithm 2), N(dst) <- N(dst) + N(src).
- * Both summaries must have the same k (else PSS_EINVAL).  Asynchronous. */
+ * Both summaries must have the same k (else PSS_EINVAL).  Asynchronous.
+ * N lives on the device with the summary: a merge queued after an update
+ * sees the N that update produced. */
 int pss_merge(pss_summary* dst, const pss_summary* src, void* stream);
 
 /* Query a summary; blocks until the result is on the host.
  * kind PSS_Q_MAJORITY: the entries with count * k > N (Algorithm 1, Pruned);
  *      if more than cap qualify, returns PSS_ETRUNC with *n_out = required.
  * kind PSS_Q_TOPK: the first min(cap, size) entries.
- * Entries are in canonical order.  *stream_len (may be NULL) receives N. */
+ * Entries are in canonical order.  *stream_len (may be NULL) receives N.
+ * Returns PSS_EDEVICE (once) when an earlier update or merge on s found a
+ * failed block and was not applied; s and N are then as before that call. */
 int pss_query(const pss_summary* s, int kind, pss_entry* h_out, uint32_t cap, uint32_t* n_out,
               uint64_t* stream_len, void* stream);
 
@@ -142,6 +158,13 @@ int pss_run(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint3
 int pss_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks,
                         const uint32_t* h_sel, uint32_t nsel, pss_entry* h_out, uint32_t* h_sizes,
                         uint64_t* h_mins, void* stream);
+
+/* Test hook for the all-or-nothing contract above: queue on `stream` a fold
+ * into s of a block summary that carries the failure mark a block kernel
+ * writes when one of its internal checks fails, as if an update of n items
+ * had produced it.  s and its N must stay as they were, and the next
+ * pss_query on s must return PSS_EDEVICE.  Uses the context's workspace. */
+int pss_test_fold_failed_block(pss_summary* s, uint64_t n, void* stream);
 
 /* ---- Batched form: many independent streams in one graph launch ----
  *

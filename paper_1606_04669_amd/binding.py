@@ -101,6 +101,8 @@ def lib():
         L.pss_query.argtypes = [vp, i32, vp, u32, u32p, u64p, vp]
         L.pss_run.argtypes = [vp, vp, u64, u32, u32, vp, u32, u32p, u32p, vp]
         L.pss_block_summaries.argtypes = [vp, vp, u64, u32, u32, u32p, u32, vp, u32p, u64p, vp]
+        L.pss_ctx_set_budget.argtypes = [vp, u64]
+        L.pss_test_fold_failed_block.argtypes = [vp, u64, vp]
         L.pss_batch_max_k.restype = u32
         L.pss_batch_max_k.argtypes = [vp]
         L.pss_batch_create.argtypes = [vp, u32, vp, u64p, u32p, u32p, i32, ctypes.POINTER(vp)]
@@ -123,7 +125,7 @@ def lib():
         for f in ("pss_timing_enable", "pss_phase_times", "pss_ctx_create", "pss_create", "pss_update", "pss_merge",
                   "pss_query", "pss_run", "pss_block_summaries", "pss_batch_create", "pss_batch_run", "pss_batch_info",
                   "pss_run_batched", "pss_server_create", "pss_server_append", "pss_server_query", "pss_server_wait",
-                  "pss_server_stats"):
+                  "pss_server_stats", "pss_ctx_set_budget", "pss_test_fold_failed_block"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -203,6 +205,10 @@ class Context:
     def plan_chunks(self, n: int, k: int) -> int:
         return int(lib().pss_plan_chunks(self.handle, n, k))
 
+    def set_budget(self, nbytes: int):
+        """Device bytes the context's workspaces may hold in all (0 = no limit)."""
+        _check(lib().pss_ctx_set_budget(self.handle, nbytes), "pss_ctx_set_budget")
+
     def timing(self, enable: bool):
         _check(lib().pss_timing_enable(self.handle, 1 if enable else 0), "pss_timing_enable")
 
@@ -273,6 +279,12 @@ def pss_query(s: Summary, kind: int = PSS_Q_MAJORITY, cap: int | None = None, st
                          ctypes.byref(slen), ctypes.c_void_p(_stream(stream)))
     _check(rc, "pss_query", int(nout.value))
     return out[: min(int(nout.value), cap)].copy(), int(slen.value)
+
+
+def pss_test_fold_failed_block(s: Summary, n: int, stream=None):
+    """Test hook: fold a block summary carrying the failure mark into s."""
+    _check(lib().pss_test_fold_failed_block(s.handle, n, ctypes.c_void_p(_stream(stream))),
+           "pss_test_fold_failed_block")
 
 
 def pss_run(ctx: Context, d_items, k: int, chunks: int = 0, cap: int | None = None, stream=None,

@@ -258,13 +258,22 @@ __global__ __launch_bounds__(kCombineThreads) void combine_level_kernel(BlockSum
     }
 }
 
+// Persistent summaries are updated all or nothing: an input carrying a
+// block's failure mark leaves d (entries, header and N) as it was and sets
+// d's fault word, which the next report hands to the host.
 template <bool G>
 __global__ __launch_bounds__(kCombineThreads) void fold_kernel(WideSummary d, BlockSummaries s, uint32_t k,
-                                                               unsigned char* scratch) {
+                                                               uint64_t n, unsigned char* scratch) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* big = G ? scratch : smem + CombineLds<uint64_t>::make(k).small_bytes;
-    combine_node<uint64_t, uint32_t, uint64_t>(d.item, d.cnt, d.err, d.size[0], d.min[0], s.item, s.cnt, s.err,
-                                               s.size[0], s.min[0], k, d.item, d.cnt, d.err, d.size, d.min, big, smem);
+    const uint32_t n1 = d.size[0], n2 = s.size[0];
+    if (n1 > k || n2 > k) {
+        if (threadIdx.x == 0) *d.fault = 1u;
+        return;
+    }
+    combine_node<uint64_t, uint32_t, uint64_t>(d.item, d.cnt, d.err, n1, d.min[0], s.item, s.cnt, s.err, n2, s.min[0],
+                                               k, d.item, d.cnt, d.err, d.size, d.min, big, smem);
+    if (threadIdx.x == 0) *d.total += n;
 }
 
 template <bool G>
@@ -272,8 +281,15 @@ __global__ __launch_bounds__(kCombineThreads) void merge_kernel(WideSummary d, W
                                                                 unsigned char* scratch) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* big = G ? scratch : smem + CombineLds<uint64_t>::make(k).small_bytes;
-    combine_node<uint64_t, uint64_t, uint64_t>(d.item, d.cnt, d.err, d.size[0], d.min[0], s.item, s.cnt, s.err,
-                                               s.size[0], s.min[0], k, d.item, d.cnt, d.err, d.size, d.min, big, smem);
+    const uint32_t n1 = d.size[0], n2 = s.size[0];
+    if (n1 > k || n2 > k) {
+        if (threadIdx.x == 0) *d.fault = 1u;
+        return;
+    }
+    const uint64_t ns = *s.total;
+    combine_node<uint64_t, uint64_t, uint64_t>(d.item, d.cnt, d.err, n1, d.min[0], s.item, s.cnt, s.err, n2, s.min[0],
+                                               k, d.item, d.cnt, d.err, d.size, d.min, big, smem);
+    if (threadIdx.x == 0) *d.total += ns;
 }
 
 // One tree level of a batch: node j merges two block summaries of one
@@ -305,29 +321,37 @@ hipError_t launch_batch_combine(const BatchNode* nodes, uint32_t count, uint32_t
 
 // Served appends: S_sid <- COMBINE(S_sid, root of the append's tree) for
 // every append of a launch (one per summary), u64 counts in the summaries.
+// A fold whose tree root carries a block's failure mark leaves its summary
+// as it was and sets *failed (the server then fails the launch).
 __global__ __launch_bounds__(kCombineThreads) void serve_fold_kernel(const ServeFold* __restrict__ f, uint32_t count,
-                                                                     WideSummary pool, BlockSummaries v) {
+                                                                     WideSummary pool, BlockSummaries v,
+                                                                     uint32_t* failed) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t small = CombineLds<uint64_t>::make(2).small_bytes;  // independent of k
     for (uint32_t j = blockIdx.x; j < count; j += gridDim.x) {
         const ServeFold d = f[j];
         __syncthreads();  // the previous fold is done with LDS
-        combine_node<uint64_t, uint32_t, uint64_t>(pool.item + d.s_off, pool.cnt + d.s_off, pool.err + d.s_off,
-                                                   pool.size[d.sid], pool.min[d.sid], v.item + d.root_off,
-                                                   v.cnt + d.root_off, v.err + d.root_off, v.size[d.root],
-                                                   v.min[d.root], d.k, pool.item + d.s_off, pool.cnt + d.s_off,
-                                                   pool.err + d.s_off, &pool.size[d.sid], &pool.min[d.sid],
-                                                   smem + small, smem);
+        const uint32_t n1 = pool.size[d.sid], n2 = v.size[d.root];
+        if (n1 > d.k || n2 > d.k) {
+            if (threadIdx.x == 0) *failed = 1u;
+            continue;
+        }
+        combine_node<uint64_t, uint32_t, uint64_t>(pool.item + d.s_off, pool.cnt + d.s_off, pool.err + d.s_off, n1,
+                                                   pool.min[d.sid], v.item + d.root_off, v.cnt + d.root_off,
+                                                   v.err + d.root_off, n2, v.min[d.root], d.k, pool.item + d.s_off,
+                                                   pool.cnt + d.s_off, pool.err + d.s_off, &pool.size[d.sid],
+                                                   &pool.min[d.sid], smem + small, smem);
     }
 }
 
 hipError_t launch_serve_fold(const ServeFold* f, uint32_t count, uint32_t kmax, const WideSummary& pool,
-                             const BlockSummaries& blocks, hipStream_t stream) {
+                             const BlockSummaries& blocks, uint32_t* failed, hipStream_t stream) {
     (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     if (count == 0) return hipSuccess;
     const uint32_t lds = combine_lds_bytes(kmax, true);
     hipFuncSetAttribute((const void*)serve_fold_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(serve_fold_kernel, dim3(count), dim3(kCombineThreads), lds, stream, f, count, pool, blocks);
+    hipLaunchKernelGGL(serve_fold_kernel, dim3(count), dim3(kCombineThreads), lds, stream, f, count, pool, blocks,
+                       failed);
     return hipGetLastError();
 }
 
@@ -362,18 +386,19 @@ hipError_t launch_combine_level(const BlockSummaries& v, uint32_t k, uint32_t co
     return hipGetLastError();
 }
 
-hipError_t launch_fold(const WideSummary& dst, const BlockSummaries& src, uint32_t k, bool in_lds,
+hipError_t launch_fold(const WideSummary& dst, const BlockSummaries& src, uint32_t k, uint64_t n, bool in_lds,
                        unsigned char* scratch, hipStream_t stream) {
     (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
+    if (!dst.total || !dst.fault) return hipErrorInvalidValue;
     const CombineLds<uint64_t> L = CombineLds<uint64_t>::make(k);
     if (in_lds) {
         const uint32_t lds = L.big_bytes + L.small_bytes;
         hipFuncSetAttribute((const void*)fold_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(fold_kernel<false>, dim3(1), dim3(kCombineThreads), lds, stream, dst, src, k,
+        hipLaunchKernelGGL(fold_kernel<false>, dim3(1), dim3(kCombineThreads), lds, stream, dst, src, k, n,
                            (unsigned char*)nullptr);
     } else {
         if (!scratch) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(fold_kernel<true>, dim3(1), dim3(kCombineThreads), L.small_bytes, stream, dst, src, k,
+        hipLaunchKernelGGL(fold_kernel<true>, dim3(1), dim3(kCombineThreads), L.small_bytes, stream, dst, src, k, n,
                            scratch);
     }
     return hipGetLastError();
@@ -382,6 +407,7 @@ hipError_t launch_fold(const WideSummary& dst, const BlockSummaries& src, uint32
 hipError_t launch_merge(const WideSummary& dst, const WideSummary& src, uint32_t k, bool in_lds,
                         unsigned char* scratch, hipStream_t stream) {
     (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
+    if (!dst.total || !dst.fault || !src.total) return hipErrorInvalidValue;
     const CombineLds<uint64_t> L = CombineLds<uint64_t>::make(k);
     if (in_lds) {
         const uint32_t lds = L.big_bytes + L.small_bytes;

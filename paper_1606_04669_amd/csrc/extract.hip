@@ -106,14 +106,23 @@ __device__ void extract_body(const uint32_t* s_item, const CT* s_cnt, const CT* 
 }
 
 // G: the sort arrays live in a global scratch slab (k beyond LDS).
+// The threshold uses the summary's own N; the report header also carries
+// the summary's fault word (cleared once read: it is reported once) and N.
 template <bool G>
-__global__ __launch_bounds__(kExtractThreads) void extract_kernel(WideSummary s, uint32_t k, uint64_t N, int kind,
-                                                                  uint32_t cap, DevEntry* out, uint32_t* out_count,
+__global__ __launch_bounds__(kExtractThreads) void extract_kernel(WideSummary s, uint32_t k, int kind, uint32_t cap,
+                                                                  DevEntry* out, uint32_t* out_count,
                                                                   unsigned char* scratch) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* base = G ? scratch : smem;
     uint32_t* small = (uint32_t*)(G ? smem : smem + extract_big_bytes(k));
+    const uint64_t N = *s.total;
+    const uint32_t fault = *s.fault;
     extract_body<uint64_t>(s.item, s.cnt, s.err, s.size[0], k, N, kind, cap, out, out_count, base, small);
+    if (threadIdx.x == 0) {
+        out_count[1] = fault;
+        *(uint64_t*)(out_count + 2) = N;
+        if (fault) *s.fault = 0u;
+    }
 }
 
 // Majority reports of a batch, one workgroup per stream, straight from the
@@ -140,6 +149,26 @@ hipError_t launch_batch_extract(const BatchReport* reps, uint32_t count, uint32_
     hipFuncSetAttribute((const void*)batch_extract_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(batch_extract_kernel, dim3(count), dim3(kExtractThreads), lds, stream, reps, count, kmax, base,
                        out, out_count);
+    return hipGetLastError();
+}
+
+// Majority report straight from a tree root (block summary 0, 32-bit
+// counts) for a stream of N items; arguments by value, nothing to stage.
+__global__ __launch_bounds__(kExtractThreads) void root_extract_kernel(BlockSummaries v, uint32_t k, uint64_t N,
+                                                                       uint32_t cap, DevEntry* out,
+                                                                       uint32_t* out_count) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* small = (uint32_t*)(smem + extract_big_bytes(k));
+    extract_body<uint32_t>(v.item, v.cnt, v.err, v.size[0], k, N, 0, cap, out, out_count, smem, small);
+}
+
+hipError_t launch_root_extract(const BlockSummaries& v, uint32_t k, uint64_t N, uint32_t cap, DevEntry* out,
+                               uint32_t* out_count, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
+    const uint32_t lds = extract_lds_bytes(k);
+    hipFuncSetAttribute((const void*)root_extract_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(root_extract_kernel, dim3(1), dim3(kExtractThreads), lds, stream, v, k, N, cap, out,
+                       out_count);
     return hipGetLastError();
 }
 
@@ -182,17 +211,18 @@ hipError_t launch_zero_words(uint32_t* p, uint32_t count, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_extract(const WideSummary& s, uint32_t k, uint64_t N, int kind, uint32_t cap, DevEntry* out,
+hipError_t launch_extract(const WideSummary& s, uint32_t k, int kind, uint32_t cap, DevEntry* out,
                           uint32_t* out_count, bool in_lds, unsigned char* scratch, hipStream_t stream) {
     (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
+    if (!s.total || !s.fault) return hipErrorInvalidValue;
     const uint32_t bytes = extract_lds_bytes(k);
     if (in_lds) {
         hipFuncSetAttribute((const void*)extract_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        hipLaunchKernelGGL(extract_kernel<false>, dim3(1), dim3(kExtractThreads), bytes, stream, s, k, N, kind, cap,
-                           out, out_count, (unsigned char*)nullptr);
+        hipLaunchKernelGGL(extract_kernel<false>, dim3(1), dim3(kExtractThreads), bytes, stream, s, k, kind, cap, out,
+                           out_count, (unsigned char*)nullptr);
     } else {
         if (!scratch) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(extract_kernel<true>, dim3(1), dim3(kExtractThreads), kExtractSmallBytes, stream, s, k, N,
+        hipLaunchKernelGGL(extract_kernel<true>, dim3(1), dim3(kExtractThreads), kExtractSmallBytes, stream, s, k,
                            kind, cap, out, out_count, scratch);
     }
     return hipGetLastError();
@@ -202,11 +232,14 @@ __global__ void reset_kernel(WideSummary s) {
     if (threadIdx.x == 0) {
         s.size[0] = 0;
         s.min[0] = 0;
+        *s.total = 0;
+        *s.fault = 0u;
     }
 }
 
 hipError_t launch_reset(const WideSummary& s, hipStream_t stream) {
     (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
+    if (!s.total || !s.fault) return hipErrorInvalidValue;
     hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, stream, s);
     return hipGetLastError();
 }

@@ -17,10 +17,6 @@
 
 using namespace pss;
 
-namespace pss {
-thread_local int t_last_device_error = 0;
-}  // namespace pss
-
 namespace {
 
 // Device memory the HBM-resident block states of one update may take; the
@@ -32,6 +28,32 @@ constexpr size_t kStateBudget = 16ull << 30;
 #define PSS_PLAN_ROUNDS 4
 #endif
 constexpr uint64_t kPlanRounds = PSS_PLAN_ROUNDS;
+
+}  // namespace
+
+namespace pss {
+thread_local int t_last_device_error = 0;
+
+uint32_t plan_chunks(int cu_count, size_t lds_per_cu, size_t lds_max, uint64_t n, uint32_t k) {
+    if (n == 0 || k < 2) return 1;
+    if (k > kMaxK) k = kMaxK;
+    // enough resident waves to cover every CU a few times over, while keeping
+    // blocks long next to k (the reduction tree moves ~C*k entries)
+    const ChunkLayout L = chunk_layout(k, lds_max);
+    uint64_t per_cu = lds_per_cu / std::max<uint32_t>(1, L.lds_bytes);
+    per_cu = std::min<uint64_t>(std::max<uint64_t>(per_cu, 1), 32);  // 32 waves per CU at most
+    // many resident waves (small k): twice the rounds, the tree stays cheap
+    uint64_t want = (uint64_t)std::max(cu_count, 1) * per_cu * (per_cu >= 8 ? 2 * kPlanRounds : kPlanRounds);
+    uint64_t cap_len = n / (16ull * k);
+    if (cap_len < 1) cap_len = 1;
+    uint64_t c = std::min(want, cap_len);
+    if (L.global_state) c = std::min<uint64_t>(c, kStateBudget / (L.state_bytes + 4ull * L.err_stride));
+    c = std::min<uint64_t>(c, kMaxChunks);
+    return (uint32_t)std::max<uint64_t>(c, 1);
+}
+}  // namespace pss
+
+namespace {
 // Concurrent COMBINE workgroups (one scratch slab each) when a COMBINE's
 // arrays do not fit LDS.
 constexpr uint32_t kCombineSlabsPerCu = 2;
@@ -41,9 +63,8 @@ constexpr uint32_t kCombineSlabsPerCu = 2;
 struct pss_summary {
     pss_ctx* ctx = nullptr;
     uint32_t k = 0;
-    uint64_t n = 0;  // stream length covered
     void* mem = nullptr;
-    WideSummary view{};
+    WideSummary view{};  // entries, header, and on the device the stream length N and the fault word
 };
 
 namespace {
@@ -73,6 +94,7 @@ size_t summary_bytes(uint32_t k) {
     return align_up((size_t)k * 4, 256) + 2 * align_up((size_t)k * 8, 256) + 256 + 256;
 }
 
+// Header block (256 B): size (u32), fault word (u32), N (u64); then min.
 WideSummary carve_summary(void* base, uint32_t k) {
     WideSummary v;
     char* p = (char*)base;
@@ -83,12 +105,26 @@ WideSummary carve_summary(void* base, uint32_t k) {
     v.err = (uint64_t*)p;
     p += align_up((size_t)k * 8, 256);
     v.size = (uint32_t*)p;
+    v.fault = (uint32_t*)(p + 4);
+    v.total = (uint64_t*)(p + 8);
     p += 256;
     v.min = (uint64_t*)p;
     return v;
 }
 
 bool k_fits(const pss_ctx*, uint32_t k) { return k >= 2 && k <= kMaxK; }
+
+size_t ctx_device_bytes(const pss_ctx* ctx) {
+    return ctx->blocks.bytes + ctx->gstate.bytes + ctx->cscratch.bytes + ctx->wscratch.bytes + ctx->query.bytes;
+}
+
+// Grows one of the context's workspaces within its device-memory budget
+// (0 = none): PSS_ENOMEM, before anything is launched, when it would not fit.
+int ctx_grow(pss_ctx* ctx, DeviceBuffer& b, size_t need) {
+    if (need <= b.bytes) return PSS_OK;
+    if (ctx->budget && ctx_device_bytes(ctx) - b.bytes + need > ctx->budget) return PSS_ENOMEM;
+    return b.grow(need);
+}
 
 // Where the arrays of each kernel live for k counters on this device.
 struct KPlan {
@@ -114,7 +150,7 @@ int ensure_wscratch(pss_ctx* ctx, const KPlan& p, uint32_t k) {
     size_t need = 0;
     if (!p.wide_lds) need = std::max(need, combine_scratch_bytes(k, true));
     if (!p.ext_lds) need = std::max(need, extract_scratch_bytes(k));
-    return need ? ctx->wscratch.grow(need) : PSS_OK;
+    return need ? ctx_grow(ctx, ctx->wscratch, need) : PSS_OK;
 }
 
 hipEvent_t take_event(pss_ctx* ctx) {
@@ -158,12 +194,12 @@ void close_phase(pss_ctx* ctx, int phase, hipEvent_t a, hipStream_t st) {
 int run_blocks(pss_ctx* ctx, const KPlan& p, const uint32_t* d_items, uint64_t n, uint32_t chunks, hipStream_t st,
                BlockSummaries* out) {
     const uint32_t k = p.L.k;
-    int rc = ctx->blocks.grow(blocks_bytes(chunks, k));
+    int rc = ctx_grow(ctx, ctx->blocks, blocks_bytes(chunks, k));
     if (rc != PSS_OK) return rc;
     // per-block scratch: the state slabs (state in device memory), then the
     // error arrays
     const size_t gbytes = p.L.global_state ? align_up((size_t)chunks * p.L.state_bytes, 256) : 0;
-    rc = ctx->gstate.grow(gbytes + (size_t)chunks * p.L.err_stride * 4);
+    rc = ctx_grow(ctx, ctx->gstate, gbytes + (size_t)chunks * p.L.err_stride * 4);
     if (rc != PSS_OK) return rc;
     unsigned char* gs = p.L.global_state ? (unsigned char*)ctx->gstate.ptr : nullptr;
     uint32_t* errs = (uint32_t*)((unsigned char*)ctx->gstate.ptr + gbytes);
@@ -219,6 +255,12 @@ int pss_phase_times(pss_ctx* ctx, double* ms, uint32_t* launches, int reset) {
 }
 
 int pss_last_device_error(void) { return pss::t_last_device_error; }
+
+int pss_ctx_set_budget(pss_ctx* ctx, uint64_t bytes) {
+    if (!ctx) return PSS_EINVAL;
+    ctx->budget = (size_t)bytes;
+    return PSS_OK;
+}
 
 const char* pss_device_error_name(int hip_error) { return hipGetErrorName((hipError_t)hip_error); }
 
@@ -290,21 +332,8 @@ uint32_t pss_max_lds_k(const pss_ctx* ctx) {
 }
 
 uint32_t pss_plan_chunks(const pss_ctx* ctx, uint64_t n, uint32_t k) {
-    if (!ctx || n == 0 || k < 2) return 1;
-    if (k > kMaxK) k = kMaxK;
-    // enough resident waves to cover every CU a few times over, while keeping
-    // blocks long next to k (the reduction tree moves ~C*k entries)
-    const ChunkLayout L = chunk_layout(k, ctx->lds_max);
-    uint64_t per_cu = ctx->lds_per_cu / std::max<uint32_t>(1, L.lds_bytes);
-    per_cu = std::min<uint64_t>(std::max<uint64_t>(per_cu, 1), 32);  // 32 waves per CU at most
-    // many resident waves (small k): twice the rounds, the tree stays cheap
-    uint64_t want = (uint64_t)ctx->cu_count * per_cu * (per_cu >= 8 ? 2 * kPlanRounds : kPlanRounds);
-    uint64_t cap_len = n / (16ull * k);
-    if (cap_len < 1) cap_len = 1;
-    uint64_t c = std::min(want, cap_len);
-    if (L.global_state) c = std::min<uint64_t>(c, kStateBudget / (L.state_bytes + 4ull * L.err_stride));
-    c = std::min<uint64_t>(c, kMaxChunks);
-    return (uint32_t)std::max<uint64_t>(c, 1);
+    if (!ctx) return 1;
+    return pss::plan_chunks(ctx->cu_count, ctx->lds_per_cu, ctx->lds_max, n, k);
 }
 
 int pss_create(pss_ctx* ctx, uint32_t k, pss_summary** out) {
@@ -361,7 +390,7 @@ int pss_update(pss_summary* s, const uint32_t* d_items, uint64_t n, uint32_t chu
     uint32_t slabs = 0;
     if (!kp.comb_lds && C > 1) {
         slabs = std::min(combine_slabs(ctx), C / 2);
-        rc = ctx->cscratch.grow((size_t)slabs * combine_scratch_bytes(k, false));
+        rc = ctx_grow(ctx, ctx->cscratch, (size_t)slabs * combine_scratch_bytes(k, false));
         if (rc != PSS_OK) return rc;
         cs = (unsigned char*)ctx->cscratch.ptr;
     }
@@ -377,10 +406,9 @@ int pss_update(pss_summary* s, const uint32_t* d_items, uint64_t n, uint32_t chu
     }
     close_phase(ctx, 1, t1, st);
     hipEvent_t t2 = mark(ctx, st);
-    rc = check(launch_fold(s->view, b, k, kp.wide_lds, (unsigned char*)ctx->wscratch.ptr, st));
+    rc = check(launch_fold(s->view, b, k, n, kp.wide_lds, (unsigned char*)ctx->wscratch.ptr, st));
     if (rc != PSS_OK) return rc;
     close_phase(ctx, 2, t2, st);
-    s->n += n;
     if (chunks_used) *chunks_used = C;
     return PSS_OK;
 }
@@ -395,9 +423,7 @@ int pss_merge(pss_summary* dst, const pss_summary* src, void* stream) {
     if (rc != PSS_OK) return rc;
     rc = check(launch_merge(dst->view, src->view, dst->k, kp.wide_lds, (unsigned char*)ctx->wscratch.ptr,
                             (hipStream_t)stream));
-    if (rc != PSS_OK) return rc;
-    dst->n += src->n;
-    return PSS_OK;
+    return rc;
 }
 
 int pss_query(const pss_summary* s, int kind, pss_entry* h_out, uint32_t cap, uint32_t* n_out,
@@ -413,7 +439,7 @@ int pss_query(const pss_summary* s, int kind, pss_entry* h_out, uint32_t cap, ui
     const KPlan kp = kplan(ctx, k);
     int rc = ensure_wscratch(ctx, kp, k);
     if (rc != PSS_OK) return rc;
-    rc = ctx->query.grow(qbytes);
+    rc = ctx_grow(ctx, ctx->query, qbytes);
     if (rc != PSS_OK) return rc;
     rc = ensure_pinned(ctx, qbytes);
     if (rc != PSS_OK) return rc;
@@ -421,16 +447,21 @@ int pss_query(const pss_summary* s, int kind, pss_entry* h_out, uint32_t cap, ui
     DevEntry* d_ent = (DevEntry*)((char*)ctx->query.ptr + 256);
     const uint32_t dev_cap = kind == PSS_Q_TOPK ? std::min(cap, k) : k;
     hipEvent_t t3 = mark(ctx, st);
-    rc = check(launch_extract(s->view, k, s->n, kind, dev_cap, d_ent, d_count, kp.ext_lds,
+    rc = check(launch_extract(s->view, k, kind, dev_cap, d_ent, d_count, kp.ext_lds,
                               (unsigned char*)ctx->wscratch.ptr, st));
     if (rc != PSS_OK) return rc;
     if (hipMemcpyAsync(ctx->pinned, ctx->query.ptr, qbytes, hipMemcpyDeviceToHost, st) != hipSuccess)
         return PSS_EDEVICE;
     close_phase(ctx, 3, t3, st);
     if (hipStreamSynchronize(st) != hipSuccess) return PSS_EDEVICE;
-    const uint32_t q = *(const uint32_t*)ctx->pinned;
+    const uint32_t q = ((const uint32_t*)ctx->pinned)[0];
+    const uint32_t fault = ((const uint32_t*)ctx->pinned)[1];
+    const uint64_t N = ((const uint64_t*)ctx->pinned)[1];
+    if (stream_len) *stream_len = N;
+    // an earlier update or merge found a failed block and left the summary as
+    // it was: reported once, here
+    if (fault) return PSS_EDEVICE;
     if (q > k) return PSS_EDEVICE;  // a kernel reported a failed invariant
-    if (stream_len) *stream_len = s->n;
     *n_out = q;
     if (kind == PSS_Q_MAJORITY && q > cap) return PSS_ETRUNC;
     const uint32_t w = std::min(q, cap);
@@ -461,10 +492,27 @@ int pss_run(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint3
     hipStream_t st = (hipStream_t)stream;
     int rc = check(launch_reset(s->view, st));
     if (rc != PSS_OK) return rc;
-    s->n = 0;
     rc = pss_update(s, d_items, n, chunks, stream, chunks_used);
     if (rc != PSS_OK) return rc;
     return pss_query(s, PSS_Q_MAJORITY, h_out, cap, n_out, nullptr, stream);
+}
+
+int pss_test_fold_failed_block(pss_summary* s, uint64_t n, void* stream) {
+    if (!s) return PSS_EINVAL;
+    pss_ctx* ctx = s->ctx;
+    const uint32_t k = s->k;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const KPlan kp = kplan(ctx, k);
+    int rc = ensure_wscratch(ctx, kp, k);
+    if (rc != PSS_OK) return rc;
+    rc = ctx_grow(ctx, ctx->blocks, blocks_bytes(1, k));
+    if (rc != PSS_OK) return rc;
+    const BlockSummaries b = carve_blocks(ctx->blocks.ptr, 1, k);
+    // the block kernel's failure mark: size 0xFFFFFFFF, minimum 0
+    if (hipMemsetAsync(b.size, 0xFF, 4, st) != hipSuccess || hipMemsetAsync(b.min, 0, 4, st) != hipSuccess)
+        return PSS_EDEVICE;
+    return check(launch_fold(s->view, b, k, n, kp.wide_lds, (unsigned char*)ctx->wscratch.ptr, st));
 }
 
 int pss_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks,

@@ -51,6 +51,10 @@ struct DeviceGuard {
     }
 };
 
+// Chunk count for n items and k counters on a device with these
+// properties (pss_plan_chunks).
+uint32_t plan_chunks(int cu_count, size_t lds_per_cu, size_t lds_max, uint64_t n, uint32_t k);
+
 // The HIP error behind the last PSS_EDEVICE returned on this thread.
 extern thread_local int t_last_device_error;
 
@@ -75,6 +79,7 @@ struct pss_ctx {
     double phase_ms[4] = {0, 0, 0, 0};
     uint32_t phase_n[4] = {0, 0, 0, 0};
     int cu_count = 0;
+    size_t budget = 0;           // device bytes the workspaces below may hold in all (0 = no limit)
     size_t lds_max = 0;          // dynamic LDS per workgroup
     size_t lds_per_cu = 0;
     pss::DeviceBuffer blocks;    // block summaries of one update

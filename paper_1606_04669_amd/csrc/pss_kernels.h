@@ -10,6 +10,10 @@ namespace pss {
 
 // A set of summaries stored at stride k (entries of summary p start at p*k),
 // with per-summary size and minimum (0 while fewer than k counters are used).
+// Persistent summaries also keep on the device the stream length N they
+// cover and a fault word: a fold or merge whose input carries a block's
+// failure mark leaves the summary and N as they were and sets the fault
+// word instead (block and tree summaries leave both null).
 template <typename CT>
 struct SummaryView {
     uint32_t* item;
@@ -17,6 +21,8 @@ struct SummaryView {
     CT* err;
     uint32_t* size;
     CT* min;
+    uint64_t* total = nullptr;
+    uint32_t* fault = nullptr;
 };
 
 using BlockSummaries = SummaryView<uint32_t>;
@@ -99,8 +105,10 @@ struct ServeQuery {
     uint32_t sid, k, kind, cap;
 };
 
+// A fold whose block-tree root carries the failure mark leaves its summary
+// as it was and sets *failed.
 hipError_t launch_serve_fold(const ServeFold* f, uint32_t count, uint32_t kmax, const WideSummary& pool,
-                             const BlockSummaries& blocks, hipStream_t stream);
+                             const BlockSummaries& blocks, uint32_t* failed, hipStream_t stream);
 hipError_t launch_serve_query(const ServeQuery* q, uint32_t count, uint32_t kmax, const WideSummary& pool,
                               DevEntry* out, uint32_t* out_count, hipStream_t stream);
 
@@ -114,26 +122,37 @@ hipError_t launch_zero_words(uint32_t* p, uint32_t count, hipStream_t stream);
 // that many workgroups run, each merging several pairs in turn.
 hipError_t launch_combine_level(const BlockSummaries& v, uint32_t k, uint32_t count, uint32_t step, bool in_lds,
                                 unsigned char* scratch, uint32_t slabs, hipStream_t stream);
-// dst <- COMBINE(dst, src) for a narrow (block/tree) src at position 0.
-hipError_t launch_fold(const WideSummary& dst, const BlockSummaries& src, uint32_t k, bool in_lds,
+// dst <- COMBINE(dst, src) for a narrow (block/tree) src at position 0, and
+// N(dst) += n; when src carries the failure mark, dst and N(dst) stay as
+// they were and dst's fault word is set.
+hipError_t launch_fold(const WideSummary& dst, const BlockSummaries& src, uint32_t k, uint64_t n, bool in_lds,
                        unsigned char* scratch, hipStream_t stream);
-// dst <- COMBINE(dst, src) for two wide summaries.
+// dst <- COMBINE(dst, src) for two wide summaries, N(dst) += N(src).
 hipError_t launch_merge(const WideSummary& dst, const WideSummary& src, uint32_t k, bool in_lds,
                         unsigned char* scratch, hipStream_t stream);
 uint32_t combine_lds_bytes(uint32_t k, bool wide);
 size_t combine_scratch_bytes(uint32_t k, bool wide);
 
-// Canonically ordered report of a wide summary: kind 0 = count*k > N,
-// kind 1 = first `cap`.  Writes entries to out and the reported count
-// (before truncation to cap for kind 0) to *out_count.
+// Canonically ordered report of a wide summary: kind 0 = count*k > N with
+// the summary's own N, kind 1 = first `cap`.  Writes entries to out and the
+// reported count (before truncation to cap for kind 0) to out_count[0], the
+// summary's fault word to out_count[1] (then clears it) and its N to
+// out_count[2..3].
 // in_lds: the sort arrays fit LDS (extract_lds_bytes <= limit); otherwise
 // scratch holds extract_scratch_bytes bytes.
-hipError_t launch_extract(const WideSummary& s, uint32_t k, uint64_t N, int kind, uint32_t cap, DevEntry* out,
+hipError_t launch_extract(const WideSummary& s, uint32_t k, int kind, uint32_t cap, DevEntry* out,
                           uint32_t* out_count, bool in_lds, unsigned char* scratch, hipStream_t stream);
 uint32_t extract_lds_bytes(uint32_t k);
 size_t extract_scratch_bytes(uint32_t k);
 
-// Set a wide summary to the empty summary.
+// Majority report (count * k > N) of the tree root v (block summary 0):
+// at most cap entries to out, the reported count (or 0xFFFFFFFF when the root
+// carries a block's failure mark) to *out_count.  The sort arrays in LDS
+// (extract_lds_bytes(k) <= the device's limit).
+hipError_t launch_root_extract(const BlockSummaries& v, uint32_t k, uint64_t N, uint32_t cap, DevEntry* out,
+                               uint32_t* out_count, hipStream_t stream);
+
+// Set a wide summary to the empty summary (N = 0, fault cleared).
 hipError_t launch_reset(const WideSummary& s, hipStream_t stream);
 
 }  // namespace pss

@@ -340,7 +340,8 @@ int run_launch(pss_server* srv, uint32_t si) {
     const size_t qb = align_up(queries.size() * sizeof(ServeQuery), 256);
     const size_t qq = 256;
     const size_t ob = align_up(out_entries * sizeof(DevEntry), 256);
-    const size_t cb = align_up((size_t)queries.size() * 4, 256);
+    // the counts of the queries, then the launch's fold-failure word
+    const size_t cb = align_up(((size_t)queries.size() + 1) * 4, 256);
     sl.off_items = 0;
     const size_t off_sum = it_b;
     sl.off_desc = off_sum + 3 * e4 + 2 * h4;
@@ -390,6 +391,7 @@ int run_launch(pss_server* srv, uint32_t si) {
     uint32_t* d_errs = (uint32_t*)(dbase + off_errs);
 
     rc = check(launch_zero_words(d_queue, kSrvClasses, st));
+    if (rc == PSS_OK) rc = check(launch_zero_words(d_counts + queries.size(), 1, st));
     for (uint32_t i = 0; rc == PSS_OK && i < nb;) {
         const uint32_t cls = hb[i].cls, first = i;
         uint32_t kc = 0;
@@ -407,7 +409,9 @@ int run_launch(pss_server* srv, uint32_t si) {
     }
     for (size_t l = 0; rc == PSS_OK && l < lvl_first.size(); ++l)
         rc = check(launch_batch_combine(d_nodes + lvl_first[l], lvl_count[l], lvl_kmax[l], sums, st));
-    if (rc == PSS_OK) rc = check(launch_serve_fold(d_folds, (uint32_t)folds.size(), fold_kmax, srv->pool, sums, st));
+    if (rc == PSS_OK)
+        rc = check(launch_serve_fold(d_folds, (uint32_t)folds.size(), fold_kmax, srv->pool, sums,
+                                     d_counts + queries.size(), st));
     if (rc == PSS_OK)
         rc = check(launch_serve_query(d_queries, (uint32_t)queries.size(), query_kmax, srv->pool, d_out, d_counts, st));
     if (rc == PSS_OK && sl.out_bytes &&
@@ -431,6 +435,12 @@ void finish_launch(pss_server* srv, Slot& sl, int rc) {
     const auto now = Clock::now();
     const char* base = (const char*)sl.pin;
     const uint32_t* counts = (const uint32_t*)(base + sl.out_bytes);
+    // a fold met a failed block: the summaries were left as they were, and the
+    // launch (and the server, as after any device failure) fails
+    if (rc == PSS_OK && counts[sl.query_index.size()] != 0) {
+        rc = PSS_EDEVICE;
+        srv->fatal = PSS_EDEVICE;
+    }
     uint64_t off = 0;
     for (uint32_t j = 0; j < sl.query_index.size(); ++j) {
         Request* q = sl.reqs[sl.query_index[j]];

@@ -192,5 +192,35 @@ def run(items, k: int, chunks: int) -> np.ndarray:
     return out[: nout.value].copy()
 
 
+def summary_threads(items, k: int, chunks: int, threads: int) -> Summary:
+    """summary() with the chunk summaries computed by `threads` threads (the
+    paper's shared-memory form, Section 3: each thread summarises its own
+    chunks with the same sequential Space Saving), then the fixed tree on one
+    thread.  Equal to summary() by construction: the chunks and the tree are
+    the same, only the order in which chunk summaries are computed differs."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    a = _items(items)
+    bounds = chunk_bounds(len(a), chunks)
+
+    def one(c):
+        b0, b1 = bounds[c]
+        return space_saving(a[b0:b1], k)
+
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        sums = list(ex.map(one, range(chunks)))
+    return tree(sums, k)
+
+
+def run_threads(items, k: int, chunks: int, threads: int) -> np.ndarray:
+    """run() on top of summary_threads()."""
+    a = _items(items)
+    if k < 2 or k > len(a):
+        raise ValueError("need 2 <= k <= n")
+    s = summary_threads(a, k, chunks, threads)
+    s.n = len(a)
+    return s.query_majority()
+
+
 def to_tuples(entries: np.ndarray):
     return [(int(e["item"]), int(e["count"]), int(e["error"])) for e in entries]

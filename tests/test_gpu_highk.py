@@ -138,3 +138,20 @@ def test_high_k_update_merge(B, ctx):
     assert B.to_tuples(got) == O.to_tuples(rs.query_majority())
     s.close()
     t.close()
+
+
+def test_high_k_combine_levels_reuse_scratch_slabs(B, ctx):
+    # k = 10^4 COMBINEs do not fit LDS: each tree level runs at most two
+    # workgroups per CU, each reusing one scratch slab for several pairs.
+    # 1200 blocks give 600 pairs at the first level, more than the slabs.
+    import os
+    items = W.zipf_hashed(1 << 24, 1.1, 1 << 32, seed=31)
+    k, C = 10000, 1200
+    say("high-k tree with slab reuse: k=%d C=%d" % (k, C))
+    got, n = whole(B, ctx, items, k, C)
+    assert n == len(items)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    assert got == O.summary_threads(items, k, C, threads).as_tuples()
+    rep, used = B.pss_run(ctx, dev(items), k=k, chunks=C)
+    assert used == C
+    assert B.to_tuples(rep) == O.to_tuples(O.run_threads(items, k, C, threads))

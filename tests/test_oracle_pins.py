@@ -264,3 +264,14 @@ def test_zipf_stream_invariants_at_plain_size():
     truth = {x for x, c in f.items() if c * k > n}
     assert truth <= rep and len(truth) >= 5
     assert int(s.entries["count"].sum()) <= n
+
+
+def test_threaded_chunk_summaries_equal_single_thread():
+    # the T-thread form (chunk summaries in parallel, tree on one thread)
+    # is the same computation as the single-threaded oracle
+    items = workloads.plain(seed=21, n=1 << 17).generate()
+    for k, C in [(100, 64), (37, 9), (500, 1), (2000, 33)]:
+        a = O.summary(items, k, C)
+        b = O.summary_threads(items, k, C, threads=4)
+        assert a.as_tuples() == b.as_tuples() and a.m == b.m
+        assert O.to_tuples(O.run(items, k, C)) == O.to_tuples(O.run_threads(items, k, C, threads=4))

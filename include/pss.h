@@ -159,6 +159,33 @@ int pss_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint3
                         const uint32_t* h_sel, uint32_t nsel, pss_entry* h_out, uint32_t* h_sizes,
                         uint64_t* h_mins, void* stream);
 
+/* pss_run without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same computation and result as pss_run with the
+ * same C, on the calling thread's current HIP device, asynchronous on
+ * `stream`, with the result left in device memory:
+ *   d_out  -- device array of cap pss_entry (caller-owned): the first
+ *             min(q, cap) reported entries in canonical order;
+ *   d_nout -- device uint32 (caller-owned): q, the number of entries with
+ *             count * k > n, or 0xFFFFFFFF when a block failed an internal
+ *             check (then d_out is not written);
+ *   *chunks_used (host, may be NULL) -- C.
+ * Its workspace is one fixed device array per GPU (pss_noalloc_scratch_bytes,
+ * 128 MiB), taken at the first call on each device and held until the
+ * process ends; no call allocates anything.  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other threads)
+ * race and must be serialised by the caller.
+ * Limits (PSS_ERANGE otherwise): 2 <= k <= n < 2^32 - 128; k within the LDS
+ * limit (pss_max_lds_k); the C blocks' summaries and error scratch,
+ * C * (12 k + 8) + 4 C * ceil32(slots(k)) bytes with about 1.7 k + 64 hash
+ * slots, within the array (e.g. k = 2000: C <= 3,500).  chunks = 0 picks
+ * pss_plan_chunks' count, lowered to fit.  PSS_EINVAL for null pointers. */
+int pss_run_noalloc(const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks, pss_entry* d_out,
+                    uint32_t cap, uint32_t* d_nout, uint32_t* chunks_used, void* stream);
+
+/* Size in bytes of pss_run_noalloc's per-device workspace array. */
+uint64_t pss_noalloc_scratch_bytes(void);
+
 /* Test hook for the all-or-nothing contract above: queue on `stream` a fold
  * into s of a block summary that carries the failure mark a block kernel
  * writes when one of its internal checks fails, as if an update of n items

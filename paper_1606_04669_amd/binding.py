@@ -102,6 +102,9 @@ def lib():
         L.pss_run.argtypes = [vp, vp, u64, u32, u32, vp, u32, u32p, u32p, vp]
         L.pss_block_summaries.argtypes = [vp, vp, u64, u32, u32, u32p, u32, vp, u32p, u64p, vp]
         L.pss_ctx_set_budget.argtypes = [vp, u64]
+        L.pss_run_noalloc.argtypes = [vp, u64, u32, u32, vp, u32, vp, u32p, vp]
+        L.pss_noalloc_scratch_bytes.restype = u64
+        L.pss_noalloc_scratch_bytes.argtypes = []
         L.pss_test_fold_failed_block.argtypes = [vp, u64, vp]
         L.pss_batch_max_k.restype = u32
         L.pss_batch_max_k.argtypes = [vp]
@@ -125,7 +128,7 @@ def lib():
         for f in ("pss_timing_enable", "pss_phase_times", "pss_ctx_create", "pss_create", "pss_update", "pss_merge",
                   "pss_query", "pss_run", "pss_block_summaries", "pss_batch_create", "pss_batch_run", "pss_batch_info",
                   "pss_run_batched", "pss_server_create", "pss_server_append", "pss_server_query", "pss_server_wait",
-                  "pss_server_stats", "pss_ctx_set_budget", "pss_test_fold_failed_block"):
+                  "pss_server_stats", "pss_ctx_set_budget", "pss_test_fold_failed_block", "pss_run_noalloc"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -279,6 +282,34 @@ def pss_query(s: Summary, kind: int = PSS_Q_MAJORITY, cap: int | None = None, st
                          ctypes.byref(slen), ctypes.c_void_p(_stream(stream)))
     _check(rc, "pss_query", int(nout.value))
     return out[: min(int(nout.value), cap)].copy(), int(slen.value)
+
+
+def pss_run_noalloc(d_items, k: int, d_out, d_nout, chunks: int = 0, stream=None, n: int | None = None) -> int:
+    """pss_run without allocation: results stay on the device (d_out: a
+    contiguous uint8 tensor of cap * 24 bytes, d_nout: one int32/uint32);
+    returns the chunk count used.  Asynchronous on `stream`."""
+    ptr, numel = _items(d_items)
+    n = numel if n is None else n
+    for t in (d_out, d_nout):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("d_out and d_nout must be contiguous device tensors")
+    if d_out.numel() * d_out.element_size() % ENTRY_DTYPE.itemsize:
+        raise ValueError("d_out must hold a whole number of 24-byte entries")
+    cap = d_out.numel() * d_out.element_size() // ENTRY_DTYPE.itemsize
+    used = ctypes.c_uint32()
+    _check(lib().pss_run_noalloc(ptr, n, k, chunks, ctypes.c_void_p(d_out.data_ptr()), cap,
+                                 ctypes.c_void_p(d_nout.data_ptr()), ctypes.byref(used),
+                                 ctypes.c_void_p(_stream(stream))), "pss_run_noalloc")
+    return int(used.value)
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().pss_noalloc_scratch_bytes())
+
+
+def entries_from_bytes(raw: np.ndarray, count: int) -> np.ndarray:
+    """The first `count` entries of a byte array holding pss_entry records."""
+    return np.frombuffer(np.ascontiguousarray(raw).tobytes(), dtype=ENTRY_DTYPE)[:count].copy()
 
 
 def pss_test_fold_failed_block(s: Summary, n: int, stream=None):

@@ -102,3 +102,54 @@ def boyer_moore_majority(items):
     if cand is not None and sum(1 for x in items if x == cand) * 2 > len(items):
         return int(cand)
     return None
+
+
+# ---------------------------------------------------------------------------
+# Frequent (Misra-Gries) for the k-majority problem (k - 1 counters), written
+# independently of frequent_oracle.c: a dict, a full pass to decrement, dict
+# merge.
+# ---------------------------------------------------------------------------
+
+def frequent(items, k):
+    """Sequential Frequent: ({item: count}, D) with D the decrement steps."""
+    ctr = {}
+    d = 0
+    for x in items:
+        x = int(x)
+        if x in ctr:
+            ctr[x] += 1
+        elif len(ctr) < k - 1:
+            ctr[x] = 1
+        else:
+            d += 1
+            ctr = {y: c - 1 for y, c in ctr.items() if c > 1}
+    return ctr, d
+
+
+def frequent_merge(s1, d1, s2, d2, k):
+    """Sum the union; beyond k - 1 items subtract the k-th largest count."""
+    u = dict(s1)
+    for x, c in s2.items():
+        u[x] = u.get(x, 0) + c
+    cut = 0
+    if len(u) > k - 1:
+        cut = sorted(u.values(), reverse=True)[k - 1]
+    return {x: c - cut for x, c in u.items() if c > cut}, d1 + d2 + cut
+
+
+def frequent_parallel(items, k, chunks):
+    """Chunk summaries, fixed tree, report of (count + D) * k > n."""
+    n = len(items)
+    nodes = []
+    for c in range(chunks):
+        lo, hi = c * n // chunks, (c + 1) * n // chunks
+        nodes.append(frequent(items[lo:hi], k))
+    step = 1
+    while step < chunks:
+        for a in range(0, chunks - step, 2 * step):
+            b = a + step
+            nodes[a] = frequent_merge(nodes[a][0], nodes[a][1], nodes[b][0], nodes[b][1], k)
+        step *= 2
+    s, d = nodes[0]
+    rep = sorted(((x, c) for x, c in s.items() if (c + d) * k > n), key=lambda t: (-t[1], t[0]))
+    return s, d, rep

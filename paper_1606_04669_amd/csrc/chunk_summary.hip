@@ -37,141 +37,27 @@
 #include <type_traits>
 
 #include "pss_device.h"
-#include "pss_layout.h"
 #include "pss_kernels.h"
+#include "pss_layout.h"
+#include "pss_table.h"
 
 namespace pss {
 
 #ifdef PSS_KERNEL_STATS
 // analysis builds only: per-phase cycle and event counts summed over waves
-__device__ unsigned long long g_kstats[24];
-#define KSTAT_DECL unsigned long long ks_[24] = {0};
+__device__ unsigned long long g_kstats[32];
+#define KSTAT_DECL unsigned long long ks_[32] = {0};
 #define KSTAT_ADD(i, v) (ks_[(i)] += (unsigned long long)(v))
 #define KSTAT_NOW() ((unsigned long long)clock64())
 #define KSTAT_FLUSH()                                                        \
     if (lane == 0)                                                           \
-        for (int i_ = 0; i_ < 24; ++i_) atomicAdd(&g_kstats[i_], ks_[i_]);
+        for (int i_ = 0; i_ < 32; ++i_) atomicAdd(&g_kstats[i_], ks_[i_]);
 #else
 #define KSTAT_DECL
 #define KSTAT_ADD(i, v) ((void)0)
 #define KSTAT_NOW() 0ull
 #define KSTAT_FLUSH()
 #endif
-
-// Table entry: key | tag << 32 with tag 0 = empty, 1 .. kTagVict - 1 = a
-// counter and its count; during a window, kTagVict + j = the counter of
-// count m that the window's j-th new item would evict, kTagPend + lane =
-// claimed by a lane (so a block holds fewer than kTagVict items).
-constexpr uint32_t kTagEmpty = 0u;
-constexpr uint32_t kTagVict = 0xFFFFFF80u;
-constexpr uint32_t kTagPend = 0xFFFFFFC0u;
-static_assert(kTagVict == kStreamBound, "every count of a block stays below the window tags");
-constexpr uint32_t kNone = 0xFFFFFFFFu;
-// Block summary size written when a loop bound that the algorithm guarantees
-// is exceeded (an internal invariant failed): the host reports a device error
-// instead of the kernel spinning.
-constexpr uint32_t kBlockFailed = 0xFFFFFFFFu;
-
-__device__ __forceinline__ uint64_t make_entry(uint32_t key, uint32_t tag) {
-    return ((uint64_t)tag << 32) | key;
-}
-
-// The hash functions of one attempt at a block.  The table only indexes the
-// counters, so every choice of multipliers gives the same summary; the first
-// attempt uses fixed ones, and a block whose items overflow a bucket pair
-// and the stash under them (possible for ids chosen to collide) is run again
-// from its start with other odd multipliers (SplitMix64 of the attempt).
-struct HashKeys {
-    uint32_t h1, h2, h3, pick;
-};
-
-constexpr uint32_t kHashAttempts = 4;
-
-__device__ __forceinline__ HashKeys hash_keys(uint32_t attempt) {
-    if (attempt == 0) return HashKeys{0x9E3779B1u, 0x85EBCA77u, 0xC2B2AE3Du, 0x2C1B3C6Du};
-    uint64_t z = (uint64_t)attempt * 0x9E3779B97F4A7C15ull;
-    uint64_t a = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    a = (a ^ (a >> 27)) * 0x94D049BB133111EBull;
-    a ^= a >> 31;
-    uint64_t b = (a + 0x9E3779B97F4A7C15ull) * 0xBF58476D1CE4E5B9ull;
-    b = (b ^ (b >> 27)) * 0x94D049BB133111EBull;
-    b ^= b >> 31;
-    return HashKeys{(uint32_t)a | 1u, (uint32_t)(a >> 32) | 1u, (uint32_t)b | 1u, (uint32_t)(b >> 32) | 1u};
-}
-
-// The two buckets of an item: multiplicative hashes scaled to nb buckets;
-// the second is moved to the neighbour of the first when they coincide.
-__device__ __forceinline__ uint32_t home_bucket(uint32_t x, uint32_t nb, const HashKeys& hk) {
-    return (uint32_t)(((uint64_t)(x * hk.h1) * nb) >> 32);
-}
-
-__device__ __forceinline__ uint32_t alt_bucket(uint32_t x, uint32_t nb, uint32_t b1, const HashKeys& hk) {
-    uint32_t h = x * hk.h2;
-    h = (h << 15) | (h >> 17);
-    const uint32_t b2 = (uint32_t)(((uint64_t)(h * hk.h3) * nb) >> 32);
-    return b2 != b1 ? b2 : (b1 + 1 == nb ? 0u : b1 + 1);
-}
-
-__device__ __forceinline__ bool live_tag(uint32_t tag) { return tag - 1u < kTagVict - 1u; }
-
-// One bucket: kBucketSlots key/tag pairs, read with kBucketSlots / 2
-// 16-byte loads.
-constexpr int kBucketQuads = (int)kBucketSlots / 2;
-struct Bucket {
-    uint4 q[kBucketQuads];
-};
-
-__device__ __forceinline__ Bucket load_bucket(const uint4* tbl4, uint32_t b) {
-    Bucket r;
-#pragma unroll
-    for (int i = 0; i < kBucketQuads; ++i) r.q[i] = tbl4[kBucketQuads * b + i];
-    return r;
-}
-
-// Slot masks (bit i = slot i of the bucket).
-__device__ __forceinline__ uint32_t match_mask(const Bucket& B, uint32_t x) {
-    uint32_t m = 0;
-#pragma unroll
-    for (int i = 0; i < kBucketQuads; ++i) {
-        m |= ((B.q[i].x == x && live_tag(B.q[i].y)) ? 1u : 0u) << (2 * i);
-        m |= ((B.q[i].z == x && live_tag(B.q[i].w)) ? 1u : 0u) << (2 * i + 1);
-    }
-    return m;
-}
-
-__device__ __forceinline__ uint32_t empty_mask(const Bucket& B) {
-    uint32_t m = 0;
-#pragma unroll
-    for (int i = 0; i < kBucketQuads; ++i) {
-        m |= (B.q[i].y == kTagEmpty ? 1u : 0u) << (2 * i);
-        m |= (B.q[i].w == kTagEmpty ? 1u : 0u) << (2 * i + 1);
-    }
-    return m;
-}
-
-// The free slot an item claims in a bucket with free-slot mask e (nonzero):
-// the (h mod popcount(e))-th free slot for a hash h of the item, so that
-// equal items pick the same slot and different items spread over the free
-// ones.
-__device__ __forceinline__ uint32_t pick_free(uint32_t e, uint32_t x, uint32_t mult) {
-    const uint32_t n = (uint32_t)__builtin_popcount(e);
-    uint32_t r = (((x * mult) >> 16) * n) >> 16;  // in [0, n)
-    for (uint32_t i = 0; i < kBucketSlots; ++i) {  // drop the r lowest set bits
-        const bool go = i < r;
-        e = go ? (e & (e - 1u)) : e;
-    }
-    return (uint32_t)__builtin_ctz(e);
-}
-
-__device__ __forceinline__ uint32_t tag_at(const Bucket& B, uint32_t i) {
-    uint32_t t = 0;
-#pragma unroll
-    for (int j = 0; j < kBucketQuads; ++j) {
-        t = (i == 2u * j) ? B.q[j].y : t;
-        t = (i == 2u * j + 1) ? B.q[j].w : t;
-    }
-    return t;
-}
 
 // ---------------------------------------------------------------------------
 // Sorting the minimum level by item id
@@ -188,6 +74,12 @@ struct SlotIds {
 __device__ __forceinline__ uint32_t slot_count(const uint32_t* words, uint32_t s) {
     const uint32_t c = words[2 * s + 1];
     return live_tag(c) ? c : 0xFFFFFFFFu;
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, uint32_t src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, (int)src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), (int)src);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, uint32_t lx) {
@@ -282,25 +174,120 @@ __device__ void sort_level_dispatch(uint16_t* list, const ID& ids, uint32_t len,
 #define SORT_FLUSH()
 #endif
 
-// Largest bucket the bucketed sort ranks directly; beyond it the level is
-// sorted with the register network instead.
+// Largest bucket the bucketed sort takes; beyond it (ids that the top digit
+// hardly separates) the level is sorted with the register network instead.
 constexpr uint32_t kMaxBucket = 48;
 
-// Bucketed sort of list[0, len) by item id for len > 64, 64 * P >= len:
-// a counting sort on 8 bits of the id (the top 8 of the bits where the
-// level's ids differ, so bucket order is id order), then every entry's rank
-// inside its bucket.  Returns false, with list as it was, when a bucket is
-// larger than kMaxBucket.  OVER: hist lies over list (the list is held in
-// registers from the first read to the final write).
-template <int P, bool OVER, typename ID>
+// Ascending bitonic sort of Q keys held by one lane.
+template <int Q>
+__device__ __forceinline__ void lane_sort(uint64_t (&v)[Q]) {
+#pragma unroll
+    for (int size = 2; size <= Q; size <<= 1) {
+#pragma unroll
+        for (int stride = size / 2; stride > 0; stride >>= 1) {
+#pragma unroll
+            for (int j = 0; j < Q; ++j) {
+                if ((j & stride) == 0) {
+                    const int j2 = j | stride;
+                    const bool up = (j & size) == 0;
+                    const uint64_t a = v[j], b = v[j2];
+                    const bool sw = (a > b) == up;
+                    v[j] = sw ? b : a;
+                    v[j2] = sw ? a : b;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);  // stage by stage: bounded live ranges
+        }
+    }
+}
+
+// A lane's bitonic sequence of Q keys into ascending order.
+template <int Q>
+__device__ __forceinline__ void lane_merge(uint64_t (&v)[Q]) {
+#pragma unroll
+    for (int stride = Q / 2; stride > 0; stride >>= 1) {
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            if ((j & stride) == 0) {
+                const int j2 = j | stride;
+                const uint64_t a = v[j], b = v[j2];
+                v[j] = a < b ? a : b;
+                v[j2] = a < b ? b : a;
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Lane l takes positions [l Q, (l+1) Q) of list/tkey (ids in tkey, slots
+// in list, in an order where only entries of one bucket can be out of
+// order), sorts them in registers by (id, slot), and odd-even merges between
+// neighbouring lanes (the lower lane keeping the smaller half) finish the
+// order; the wave stops as soon as every lane's last key is at most its
+// neighbour's first, after at most 64 rounds (odd-even transposition over 64
+// blocks sorts any input).  Out of line: its registers stay apart from the
+// caller's.
+template <int Q>
+__device__ __attribute__((noinline)) void merge_runs(uint16_t* list, const uint32_t* tkey, uint32_t len,
+                                                     uint32_t lane) {
+    uint64_t v[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const uint32_t g = lane * Q + j;
+        const uint32_t gi = g < len ? g : 0u;
+        const uint64_t key = ((uint64_t)tkey[gi] << 32) | list[gi];
+        v[j] = g < len ? key : ~0ull;
+    }
+    lane_sort<Q>(v);
+    const uint32_t up = lane + 1 < kWave ? lane + 1 : lane;
+    for (uint32_t round = 0; round < kWave; ++round) {
+        const uint64_t next_first = shfl_u64(v[0], up);
+        if (ballot(lane + 1 < kWave && v[Q - 1] > next_first) == 0) break;
+        // pairs (2i + off, 2i + 1 + off): merge, the lower lane keeping the
+        // smaller half (its partner's run is read in reverse, which makes the
+        // pair's keys a bitonic sequence)
+        const uint32_t off = round & 1u;
+        const bool lower = ((lane - off) & 1u) == 0u;
+        const uint32_t partner = lower ? lane + 1 : lane - 1;
+        const bool paired = lane >= off && partner < kWave;
+        const uint32_t src = paired ? partner : lane;
+        // registers j and Q-1-j pair with the partner's Q-1-j and j: read
+        // both before either is replaced
+#pragma unroll
+        for (int j = 0; j < Q / 2; ++j) {
+            const int jj = Q - 1 - j;
+            const uint64_t ta = shfl_u64(v[jj], src);
+            const uint64_t tb = shfl_u64(v[j], src);
+            const uint64_t lo_a = v[j] < ta ? v[j] : ta, hi_a = v[j] < ta ? ta : v[j];
+            const uint64_t lo_b = v[jj] < tb ? v[jj] : tb, hi_b = v[jj] < tb ? tb : v[jj];
+            v[j] = !paired ? v[j] : (lower ? lo_a : hi_a);
+            v[jj] = !paired ? v[jj] : (lower ? lo_b : hi_b);
+        }
+        lane_merge<Q>(v);
+    }
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const uint32_t g = lane * Q + j;
+        if (g < len) list[g] = (uint16_t)v[j];
+    }
+}
+
+// Bucketed sort of list[0, len) by item id for len > 64, 64 * Q >= len: a
+// counting sort on 8 bits of the id (the top 8 of the bits where the level's
+// ids differ, so bucket order is id order) places every entry in its bucket;
+// then merge_runs orders the entries inside each bucket.  Returns false, with list as it was, when a bucket is larger than
+// kMaxBucket.  OVER: hist lies over list (the list is held in registers
+// from the first read to the scatter).
+template <int Q, bool OVER, typename ID>
 __device__ bool sort_level_buckets(uint16_t* list, const ID& ids, uint32_t* tkey, uint32_t* hist,
                                    uint32_t len, uint32_t lane) {
-    uint32_t sd[P], id[P], pin[P];
+    uint32_t sd[Q], id[Q], pin[Q];
     uint32_t orv = 0u, andv = 0xFFFFFFFFu;
     SORT_T(0);
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const uint32_t g = lane * P + j;
+    for (int j = 0; j < Q; ++j) {
+        const uint32_t g = lane * Q + j;
         const uint32_t s = list[g < len ? g : 0u];
         id[j] = ids(s);
         sd[j] = s;
@@ -316,8 +303,8 @@ __device__ bool sort_level_buckets(uint16_t* list, const ID& ids, uint32_t* tkey
     for (uint32_t i = lane; i < 257; i += kWave) hist[i] = 0u;
     wave_sync();
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const uint32_t g = lane * P + j;
+    for (int j = 0; j < Q; ++j) {
+        const uint32_t g = lane * Q + j;
         const uint32_t d = (id[j] >> shift) & 255u;
         sd[j] |= d << 16;
         pin[j] = (g < len) ? atomicAdd(&hist[d], 1u) : 0u;
@@ -329,15 +316,15 @@ __device__ bool sort_level_buckets(uint16_t* list, const ID& ids, uint32_t* tkey
         if constexpr (OVER) {  // put the list back for the fallback
             wave_sync();
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
-                const uint32_t g = lane * P + j;
+            for (int j = 0; j < Q; ++j) {
+                const uint32_t g = lane * Q + j;
                 if (g < len) list[g] = (uint16_t)(sd[j] & 0xFFFFu);
             }
             wave_sync();
         }
         return false;
     }
-    // exclusive scan of the 256 counts: bucket d occupies [hist[d], hist[d+1])
+    // exclusive scan of the 256 counts: bucket d starts at hist[d]
     const uint32_t sum = h0 + h1 + h2 + h3;
     uint32_t incl = sum;
     for (int off = 1; off < 64; off <<= 1) {
@@ -350,46 +337,22 @@ __device__ bool sort_level_buckets(uint16_t* list, const ID& ids, uint32_t* tkey
     hist[4 * lane + 1] = ex + h0;
     hist[4 * lane + 2] = ex + h0 + h1;
     hist[4 * lane + 3] = ex + h0 + h1 + h2;
-    if (lane == 63) hist[256] = incl;
     wave_sync();
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const uint32_t g = lane * P + j;
-        if (g < len) tkey[hist[sd[j] >> 16] + pin[j]] = id[j];
-    }
-    wave_sync();
-    SORT_T(3);
+    for (int j = 0; j < Q; ++j) pin[j] += hist[sd[j] >> 16];  // the entry's place in bucket order
+    wave_sync();  // the histogram is read: list may now overwrite it
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const uint32_t g = lane * P + j;
+    for (int j = 0; j < Q; ++j) {
+        const uint32_t g = lane * Q + j;
         if (g < len) {
-            const uint32_t d = sd[j] >> 16;
-            const uint32_t b0 = hist[d], b1 = hist[d + 1];
-            uint32_t r = 0;
-            if constexpr (OVER) {
-                // four ids per step, their loads in flight together (addresses
-                // past the bucket's end are clamped to its first entry)
-                for (uint32_t t = b0; t < b1; t += 4) {
-                    const uint32_t k0 = tkey[t];
-                    const uint32_t k1 = tkey[t + 1 < b1 ? t + 1 : b0];
-                    const uint32_t k2 = tkey[t + 2 < b1 ? t + 2 : b0];
-                    const uint32_t k3 = tkey[t + 3 < b1 ? t + 3 : b0];
-                    r += (k0 < id[j] ? 1u : 0u) + ((t + 1 < b1 && k1 < id[j]) ? 1u : 0u) +
-                         ((t + 2 < b1 && k2 < id[j]) ? 1u : 0u) + ((t + 3 < b1 && k3 < id[j]) ? 1u : 0u);
-                }
-            } else {
-                for (uint32_t t = b0; t < b1; ++t) r += tkey[t] < id[j] ? 1u : 0u;
-            }
-            pin[j] = b0 + r;
+            tkey[pin[j]] = id[j];
+            list[pin[j]] = (uint16_t)(sd[j] & 0xFFFFu);
         }
     }
     wave_sync();
+    SORT_T(3);
+    merge_runs<Q>(list, tkey, len, lane);
     SORT_T(4);
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const uint32_t g = lane * P + j;
-        if (g < len) list[pin[j]] = (uint16_t)(sd[j] & 0xFFFFu);
-    }
     SORT_T(5);
     SORT_FLUSH();
     return true;
@@ -638,54 +601,6 @@ __device__ __forceinline__ uint64_t build_level_global(unsigned char* sb, unsign
 }
 
 // ---------------------------------------------------------------------------
-// Input staging
-// ---------------------------------------------------------------------------
-
-// Four consecutive items at idx (a multiple of 4), zero at and beyond stop.
-// The input is read once: loads are marked non-temporal so that the stream
-// does not push the blocks' error scratch out of the L2.
-#ifndef PSS_INPUT_TEMPORAL
-#define PSS_NT_LOAD(p) __builtin_nontemporal_load(p)
-#else
-#define PSS_NT_LOAD(p) (*(p))
-#endif
-typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ uint4 load4(const uint32_t* __restrict__ items, uint64_t idx, uint64_t n, uint64_t stop,
-                                       int vec_ok) {
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (idx >= stop) return v;
-    if (vec_ok && idx + 3 < n) {
-        const u32x4_t t = PSS_NT_LOAD((const u32x4_t*)(items + idx));
-        v = make_uint4(t[0], t[1], t[2], t[3]);
-    } else {
-        if (idx < n) v.x = PSS_NT_LOAD(items + idx);
-        if (idx + 1 < n) v.y = PSS_NT_LOAD(items + idx + 1);
-        if (idx + 2 < n) v.z = PSS_NT_LOAD(items + idx + 2);
-        if (idx + 3 < n) v.w = PSS_NT_LOAD(items + idx + 3);
-    }
-    return v;
-}
-
-// One half of the ring: 256 items, four per lane.
-static_assert(kRingHalf == 4 * kWave, "one uint4 per lane per ring half");
-struct Prefetch {
-    uint4 a;
-};
-
-__device__ __forceinline__ Prefetch fetch_half(const uint32_t* __restrict__ items, uint64_t tile, uint64_t n,
-                                               uint64_t stop, int vec_ok, uint32_t lane) {
-    Prefetch p;
-    p.a = load4(items, tile + 4 * lane, n, stop, vec_ok);
-    return p;
-}
-
-__device__ __forceinline__ void store_half(uint32_t* ring, uint64_t tile, const Prefetch& p, uint32_t lane) {
-    uint32_t base = (uint32_t)tile & (kRing - 1);
-    *(uint4*)(ring + base + 4 * lane) = p.a;
-}
-
-// ---------------------------------------------------------------------------
 // The kernel
 // ---------------------------------------------------------------------------
 
@@ -866,6 +781,9 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
         //    slots.  Every lost swap removes a slot from the view, so the loop
         //    ends within 16 + 64 rounds.  The claimed slot becomes the new
         //    counter if the item is installed.
+#ifdef PSS_KERNEL_STATS
+        uint32_t steps_seen = 0;
+#endif
         if (miss) {
             const uint64_t mine = make_entry(x, kTagPend + lane);
             uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2);
@@ -874,8 +792,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
                 uint32_t h = kNone;
                 bool join = false;
                 if (e1 | e2) {
-                    h = __builtin_popcount(e1) >= __builtin_popcount(e2) ? kBucketSlots * b1 + pick_free(e1, x, hk.pick)
-                                                                         : kBucketSlots * b2 + pick_free(e2, x, hk.pick);
+                    h = claim_slot(e1, e2, b1, b2, x, hk.pick);
                 } else {
                     // both buckets full: the value's claim, or a free slot, in the stash
                     uint32_t fe = kNone;
@@ -922,7 +839,14 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
                     break;
                 }
             }
+#ifdef PSS_KERNEL_STATS
+            steps_seen = steps + 1;
+#endif
         }
+        KSTAT_ADD(26, KSTAT_NOW() - tp);
+#ifdef PSS_KERNEL_STATS
+        KSTAT_ADD(27, wave_max_u32(steps_seen));
+#endif
         if (ballot(bad)) {
             failed = ballot(nofree) ? 2u : 1u;  // 2: the hash functions, not the algorithm
             continue;
@@ -986,6 +910,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
         }
         wave_sync();
         KSTAT_ADD(6, KSTAT_NOW() - tv);
+        const unsigned long long tq = KSTAT_NOW();
 
         const uint32_t rep = miss ? (((const volatile uint32_t*)words)[2 * hp + 1] - kTagPend) : lane;
         // a hit on a counter tagged as the j-th victim: jmark = j + 1
@@ -1020,6 +945,8 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
         //    becomes the counter in its claimed slot (count 1, or m + 1 with
         //    error m when it replaces a victim); a repeat adds 1 to its
         //    value's new counter; claims past the prefix are released
+        KSTAT_ADD(24, KSTAT_NOW() - tq);
+        const unsigned long long ta = KSTAT_NOW();
         const uint64_t inmask = (p >= kWave) ? ~0ull : ((1ull << p) - 1ull);
         const uint32_t rp = popc64(newmask & inmask);
         if (full) {
@@ -1065,6 +992,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
         pos += p;
         xn = ring[(uint32_t)(pos + lane) & (kRing - 1)];
         wave_sync();
+        KSTAT_ADD(25, KSTAT_NOW() - ta);
         KSTAT_ADD(3, KSTAT_NOW() - tw);
         KSTAT_ADD(11, p < wl ? 1 : 0);
         KSTAT_ADD(14, r);
@@ -1231,7 +1159,7 @@ hipError_t launch_batch_blocks(const BatchBlock* blocks, uint32_t nblocks, uint3
 extern "C" int pss_debug_kstats(unsigned long long* out, int reset) {
     if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_kstats), sizeof(g_kstats)) != hipSuccess) return -6;
     if (reset) {
-        unsigned long long z[24] = {0};
+        unsigned long long z[32] = {0};
         if (hipMemcpyToSymbol(HIP_SYMBOL(g_kstats), z, sizeof(z)) != hipSuccess) return -6;
     }
     return 0;

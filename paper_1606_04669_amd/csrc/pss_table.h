@@ -1,0 +1,202 @@
+// The block kernels' hash table of counters and their input staging, shared
+// by the Space Saving and the Frequent block kernels.
+//
+// A counter is a slot of a two-choice hash table: its 64-bit entry holds the
+// item id (low word) and the count (high word); count 0 marks an empty slot
+// and the top 128 count values are tags a window uses for victims and
+// claims.  An item lives in one of the 8-slot buckets its two hash functions
+// pick, or in a 64-slot stash after them when both are full.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pss_device.h"
+#include "pss_layout.h"
+
+namespace pss {
+
+// Table entry: key | tag << 32 with tag 0 = empty, 1 .. kTagVict - 1 = a
+// counter and its count; during a window, kTagVict + j = the counter of
+// count m that the window's j-th new item would evict, kTagPend + lane =
+// claimed by a lane (so a block holds fewer than kTagVict items).
+constexpr uint32_t kTagEmpty = 0u;
+constexpr uint32_t kTagVict = 0xFFFFFF80u;
+constexpr uint32_t kTagPend = 0xFFFFFFC0u;
+static_assert(kTagVict == kStreamBound, "every count of a block stays below the window tags");
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+// Block summary size written when a loop bound that the algorithm guarantees
+// is exceeded (an internal invariant failed): the host reports a device error
+// instead of the kernel spinning.
+constexpr uint32_t kBlockFailed = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint64_t make_entry(uint32_t key, uint32_t tag) {
+    return ((uint64_t)tag << 32) | key;
+}
+
+// The hash functions of one attempt at a block.  The table only indexes the
+// counters, so every choice of multipliers gives the same summary; the first
+// attempt uses fixed ones, and a block whose items overflow a bucket pair
+// and the stash under them (possible for ids chosen to collide) is run again
+// from its start with other odd multipliers (SplitMix64 of the attempt).
+struct HashKeys {
+    uint32_t h1, h2, h3, pick;
+};
+
+constexpr uint32_t kHashAttempts = 4;
+
+__device__ __forceinline__ HashKeys hash_keys(uint32_t attempt) {
+    if (attempt == 0) return HashKeys{0x9E3779B1u, 0x85EBCA77u, 0xC2B2AE3Du, 0x2C1B3C6Du};
+    uint64_t z = (uint64_t)attempt * 0x9E3779B97F4A7C15ull;
+    uint64_t a = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    a = (a ^ (a >> 27)) * 0x94D049BB133111EBull;
+    a ^= a >> 31;
+    uint64_t b = (a + 0x9E3779B97F4A7C15ull) * 0xBF58476D1CE4E5B9ull;
+    b = (b ^ (b >> 27)) * 0x94D049BB133111EBull;
+    b ^= b >> 31;
+    return HashKeys{(uint32_t)a | 1u, (uint32_t)(a >> 32) | 1u, (uint32_t)b | 1u, (uint32_t)(b >> 32) | 1u};
+}
+
+// The two buckets of an item: multiplicative hashes scaled to nb buckets;
+// the second is moved to the neighbour of the first when they coincide.
+__device__ __forceinline__ uint32_t home_bucket(uint32_t x, uint32_t nb, const HashKeys& hk) {
+    return (uint32_t)(((uint64_t)(x * hk.h1) * nb) >> 32);
+}
+
+__device__ __forceinline__ uint32_t alt_bucket(uint32_t x, uint32_t nb, uint32_t b1, const HashKeys& hk) {
+    uint32_t h = x * hk.h2;
+    h = (h << 15) | (h >> 17);
+    const uint32_t b2 = (uint32_t)(((uint64_t)(h * hk.h3) * nb) >> 32);
+    return b2 != b1 ? b2 : (b1 + 1 == nb ? 0u : b1 + 1);
+}
+
+__device__ __forceinline__ bool live_tag(uint32_t tag) { return tag - 1u < kTagVict - 1u; }
+
+// One bucket: kBucketSlots key/tag pairs, read with kBucketSlots / 2
+// 16-byte loads.
+constexpr int kBucketQuads = (int)kBucketSlots / 2;
+struct Bucket {
+    uint4 q[kBucketQuads];
+};
+
+__device__ __forceinline__ Bucket load_bucket(const uint4* tbl4, uint32_t b) {
+    Bucket r;
+#pragma unroll
+    for (int i = 0; i < kBucketQuads; ++i) r.q[i] = tbl4[kBucketQuads * b + i];
+    return r;
+}
+
+// Slot masks (bit i = slot i of the bucket).
+__device__ __forceinline__ uint32_t match_mask(const Bucket& B, uint32_t x) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < kBucketQuads; ++i) {
+        m |= ((B.q[i].x == x && live_tag(B.q[i].y)) ? 1u : 0u) << (2 * i);
+        m |= ((B.q[i].z == x && live_tag(B.q[i].w)) ? 1u : 0u) << (2 * i + 1);
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint32_t empty_mask(const Bucket& B) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < kBucketQuads; ++i) {
+        m |= (B.q[i].y == kTagEmpty ? 1u : 0u) << (2 * i);
+        m |= (B.q[i].w == kTagEmpty ? 1u : 0u) << (2 * i + 1);
+    }
+    return m;
+}
+
+// The free slot an item claims in a bucket with free-slot mask e (nonzero):
+// the (h mod popcount(e))-th free slot for a hash h of the item, so that
+// equal items pick the same slot and different items spread over the free
+// ones.
+__device__ __forceinline__ uint32_t pick_free(uint32_t e, uint32_t x, uint32_t mult) {
+    static_assert(kBucketSlots == 8, "the rank search below covers 8 slots");
+    const uint32_t n = (uint32_t)__builtin_popcount(e);
+    uint32_t r = (((x * mult) >> 16) * n) >> 16;  // in [0, n)
+    // the r-th set bit: halve the window three times by popcounts
+    uint32_t base = 0;
+    uint32_t c = (uint32_t)__builtin_popcount(e & 0xFu);
+    bool up = r >= c;
+    base = up ? 4u : 0u;
+    r = up ? r - c : r;
+    e = up ? e >> 4 : e;
+    c = (uint32_t)__builtin_popcount(e & 0x3u);
+    up = r >= c;
+    base += up ? 2u : 0u;
+    r = up ? r - c : r;
+    e = up ? e >> 2 : e;
+    return base + ((r >= (e & 1u)) ? 1u : 0u);
+}
+
+// The slot a missing item claims: a free slot of the emptier of its two
+// buckets (the first on ties), chosen by pick_free; kNone when both are full.
+__device__ __forceinline__ uint32_t claim_slot(uint32_t e1, uint32_t e2, uint32_t b1, uint32_t b2, uint32_t x,
+                                               uint32_t mult) {
+    const bool first = __builtin_popcount(e1) >= __builtin_popcount(e2);
+    const uint32_t e = first ? e1 : e2;
+    const uint32_t b = first ? b1 : b2;
+    return e ? kBucketSlots * b + pick_free(e, x, mult) : kNone;
+}
+
+__device__ __forceinline__ uint32_t tag_at(const Bucket& B, uint32_t i) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int j = 0; j < kBucketQuads; ++j) {
+        t = (i == 2u * j) ? B.q[j].y : t;
+        t = (i == 2u * j + 1) ? B.q[j].w : t;
+    }
+    return t;
+}
+
+
+// ---------------------------------------------------------------------------
+// Input staging
+// ---------------------------------------------------------------------------
+
+// Four consecutive items at idx (a multiple of 4), zero at and beyond stop.
+// The input is read once: loads are marked non-temporal so that the stream
+// does not push the blocks' error scratch out of the L2.
+#ifndef PSS_INPUT_TEMPORAL
+#define PSS_NT_LOAD(p) __builtin_nontemporal_load(p)
+#else
+#define PSS_NT_LOAD(p) (*(p))
+#endif
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint4 load4(const uint32_t* __restrict__ items, uint64_t idx, uint64_t n, uint64_t stop,
+                                       int vec_ok) {
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (idx >= stop) return v;
+    if (vec_ok && idx + 3 < n) {
+        const u32x4_t t = PSS_NT_LOAD((const u32x4_t*)(items + idx));
+        v = make_uint4(t[0], t[1], t[2], t[3]);
+    } else {
+        if (idx < n) v.x = PSS_NT_LOAD(items + idx);
+        if (idx + 1 < n) v.y = PSS_NT_LOAD(items + idx + 1);
+        if (idx + 2 < n) v.z = PSS_NT_LOAD(items + idx + 2);
+        if (idx + 3 < n) v.w = PSS_NT_LOAD(items + idx + 3);
+    }
+    return v;
+}
+
+// One half of the ring: 256 items, four per lane.
+static_assert(kRingHalf == 4 * kWave, "one uint4 per lane per ring half");
+struct Prefetch {
+    uint4 a;
+};
+
+__device__ __forceinline__ Prefetch fetch_half(const uint32_t* __restrict__ items, uint64_t tile, uint64_t n,
+                                               uint64_t stop, int vec_ok, uint32_t lane) {
+    Prefetch p;
+    p.a = load4(items, tile + 4 * lane, n, stop, vec_ok);
+    return p;
+}
+
+__device__ __forceinline__ void store_half(uint32_t* ring, uint64_t tile, const Prefetch& p, uint32_t lane) {
+    uint32_t base = (uint32_t)tile & (kRing - 1);
+    *(uint4*)(ring + base + 4 * lane) = p.a;
+}
+
+}  // namespace pss

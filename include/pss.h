@@ -108,6 +108,18 @@ int pss_ctx_set_budget(pss_ctx* ctx, uint64_t bytes);
  * given chunks = 0 (a deterministic function of n, k and the device). */
 uint32_t pss_plan_chunks(const pss_ctx* ctx, uint64_t n, uint32_t k);
 
+/* Autotuner for the chunk count C (Algorithm 1's number of blocks), the one
+ * parameter that changes results: times the block summaries and the
+ * reduction tree over d_items[0, n) with k counters for C in {P/4, P/2, P,
+ * 2P}, P = pss_plan_chunks(n, k) (one warm-up and the best of two timed runs
+ * each), and returns the fastest in *best_chunks (its time in *best_ms, may
+ * be NULL).  Pass the result as `chunks` to pss_update / pss_run and record
+ * it: a CPU replay with the same C reproduces the results.  Every call
+ * times afresh (the best C depends on the data).  Blocks until done; uses the
+ * context's workspace.  PSS_ERANGE for n = 0, n >= 2^32 - 128 or k > pss_max_k(). */
+int pss_tune_chunks(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, void* stream,
+                    uint32_t* best_chunks, double* best_ms);
+
 /* Create an empty summary with k counters (2 <= k <= pss_max_k()).
  * Empty means N = 0 and no monitored items: the identity of COMBINE. */
 int pss_create(pss_ctx* ctx, uint32_t k, pss_summary** out);
@@ -186,12 +198,59 @@ int pss_run_noalloc(const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t ch
 /* Size in bytes of pss_run_noalloc's per-device workspace array. */
 uint64_t pss_noalloc_scratch_bytes(void);
 
+/* Measurement helper: the read bandwidth (GB/s, 10^9 bytes/s) a plain
+ * streaming kernel reaches over the device buffer d_buf[0, bytes) (16-byte
+ * aligned), the best of `reps` timed launches after a warm-up; the
+ * reference the block kernel's read roofline is compared against next to
+ * the published peak.  Reads only; uses the context's report buffer as a
+ * (never written) sink.  Blocks until done. */
+int pss_read_bandwidth(pss_ctx* ctx, const void* d_buf, uint64_t bytes, uint32_t reps, void* stream, double* gbps);
+
 /* Test hook for the all-or-nothing contract above: queue on `stream` a fold
  * into s of a block summary that carries the failure mark a block kernel
  * writes when one of its internal checks fails, as if an update of n items
  * had produced it.  s and its N must stay as they were, and the next
  * pss_query on s must return PSS_EDEVICE.  Uses the context's workspace. */
 int pss_test_fold_failed_block(pss_summary* s, uint64_t n, void* stream);
+
+/* ---- Frequent (Misra-Gries) in the same pipeline ----
+ *
+ * Section 2 of the paper names Frequent as the counter-based summary whose
+ * parallel merge the authors built before Space Saving.  For the k-majority
+ * problem it keeps k - 1 counters: a monitored item adds 1; an unmonitored
+ * one takes a free counter with count 1, else every counter loses 1 (those
+ * at 0 are freed) and the item is dropped; D counts these decrement steps,
+ * so f - D <= count <= f and D * k <= n.  Summaries merge by adding the
+ * counts of the union and, beyond k - 1 items, subtracting the k-th largest
+ * count c from all and keeping the positive ones (D = D1 + D2 + c).  The
+ * parallel form is Algorithm 1 with this merge: the same blocks for the same
+ * C, the same fixed tree; results depend only on n, k and C.  Entries carry
+ * error 0 (D bounds every entry). */
+
+/* Largest k of the Frequent path on this context's device (its block state,
+ * merges and report in LDS); 0 for a null ctx. */
+uint32_t pss_frequent_max_k(const pss_ctx* ctx);
+
+/* Parallel Frequent over the device array d_items[0, n), k - 1 counters per
+ * block, C = chunks blocks (0: pss_plan_chunks).  kind PSS_Q_MAJORITY: the
+ * entries with (count + D) * k > n (every true k-majority item is among
+ * them), PSS_ETRUNC with *n_out = required when more than cap; kind
+ * PSS_Q_TOPK: the first min(cap, size) entries of the merged summary.  Order:
+ * count descending, item ascending.  *h_decrements (may be NULL) receives
+ * the merged summary's D, *chunks_used (may be NULL) C.  Requires
+ * 2 <= k <= n < 2^32 - 128 and k <= pss_frequent_max_k() (else PSS_ERANGE).
+ * Blocks until the result is on the host; uses the context's workspace. */
+int pss_frequent_run(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks, int kind,
+                     pss_entry* h_out, uint32_t cap, uint32_t* n_out, uint64_t* h_decrements, uint32_t* chunks_used,
+                     void* stream);
+
+/* Frequent block summaries (before the tree) of the nsel blocks listed in
+ * h_sel: entries of block h_sel[i] to h_out + i*k (any order, error 0), its
+ * size (<= k - 1) to h_sizes[i], its D to h_decrements[i].  Blocks until
+ * done. */
+int pss_frequent_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks,
+                                 const uint32_t* h_sel, uint32_t nsel, pss_entry* h_out, uint32_t* h_sizes,
+                                 uint64_t* h_decrements, void* stream);
 
 /* ---- Batched form: many independent streams in one graph launch ----
  *

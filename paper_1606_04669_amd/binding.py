@@ -102,6 +102,12 @@ def lib():
         L.pss_run.argtypes = [vp, vp, u64, u32, u32, vp, u32, u32p, u32p, vp]
         L.pss_block_summaries.argtypes = [vp, vp, u64, u32, u32, u32p, u32, vp, u32p, u64p, vp]
         L.pss_ctx_set_budget.argtypes = [vp, u64]
+        L.pss_read_bandwidth.argtypes = [vp, vp, u64, u32, vp, ctypes.POINTER(ctypes.c_double)]
+        L.pss_frequent_max_k.restype = u32
+        L.pss_frequent_max_k.argtypes = [vp]
+        L.pss_frequent_run.argtypes = [vp, vp, u64, u32, u32, i32, vp, u32, u32p, u64p, u32p, vp]
+        L.pss_frequent_block_summaries.argtypes = [vp, vp, u64, u32, u32, u32p, u32, vp, u32p, u64p, vp]
+        L.pss_tune_chunks.argtypes = [vp, vp, u64, u32, vp, u32p, ctypes.POINTER(ctypes.c_double)]
         L.pss_run_noalloc.argtypes = [vp, u64, u32, u32, vp, u32, vp, u32p, vp]
         L.pss_noalloc_scratch_bytes.restype = u64
         L.pss_noalloc_scratch_bytes.argtypes = []
@@ -128,7 +134,8 @@ def lib():
         for f in ("pss_timing_enable", "pss_phase_times", "pss_ctx_create", "pss_create", "pss_update", "pss_merge",
                   "pss_query", "pss_run", "pss_block_summaries", "pss_batch_create", "pss_batch_run", "pss_batch_info",
                   "pss_run_batched", "pss_server_create", "pss_server_append", "pss_server_query", "pss_server_wait",
-                  "pss_server_stats", "pss_ctx_set_budget", "pss_test_fold_failed_block", "pss_run_noalloc"):
+                  "pss_server_stats", "pss_ctx_set_budget", "pss_test_fold_failed_block", "pss_tune_chunks", "pss_read_bandwidth", "pss_frequent_run",
+                  "pss_frequent_block_summaries", "pss_run_noalloc"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -207,6 +214,29 @@ class Context:
 
     def plan_chunks(self, n: int, k: int) -> int:
         return int(lib().pss_plan_chunks(self.handle, n, k))
+
+    def tune_chunks(self, d_items, k: int, stream=None, n: int | None = None):
+        """pss_tune_chunks: (chunk count, ms of blocks + tree at that count)."""
+        ptr, numel = _items(d_items)
+        n = numel if n is None else n
+        best, ms = ctypes.c_uint32(), ctypes.c_double()
+        _check(lib().pss_tune_chunks(self.handle, ptr, n, k, ctypes.c_void_p(_stream(stream)), ctypes.byref(best),
+                                     ctypes.byref(ms)), "pss_tune_chunks")
+        return int(best.value), float(ms.value)
+
+    def read_bandwidth(self, d_buf, reps: int = 5, stream=None) -> float:
+        """pss_read_bandwidth over a contiguous device tensor: GB/s."""
+        if not isinstance(d_buf, torch.Tensor) or not d_buf.is_cuda or not d_buf.is_contiguous():
+            raise TypeError("d_buf must be a contiguous device tensor")
+        g = ctypes.c_double()
+        _check(lib().pss_read_bandwidth(self.handle, ctypes.c_void_p(d_buf.data_ptr()),
+                                        d_buf.numel() * d_buf.element_size(), reps,
+                                        ctypes.c_void_p(_stream(stream)), ctypes.byref(g)), "pss_read_bandwidth")
+        return float(g.value)
+
+    @property
+    def frequent_max_k(self) -> int:
+        return int(lib().pss_frequent_max_k(self.handle))
 
     def set_budget(self, nbytes: int):
         """Device bytes the context's workspaces may hold in all (0 = no limit)."""
@@ -310,6 +340,40 @@ def noalloc_scratch_bytes() -> int:
 def entries_from_bytes(raw: np.ndarray, count: int) -> np.ndarray:
     """The first `count` entries of a byte array holding pss_entry records."""
     return np.frombuffer(np.ascontiguousarray(raw).tobytes(), dtype=ENTRY_DTYPE)[:count].copy()
+
+
+def pss_frequent_run(ctx: Context, d_items, k: int, chunks: int = 0, kind: int = PSS_Q_MAJORITY,
+                     cap: int | None = None, stream=None, n: int | None = None):
+    """Parallel Frequent: (entries, D, chunk count used)."""
+    ptr, numel = _items(d_items)
+    n = numel if n is None else n
+    cap = k if cap is None else cap
+    out = np.zeros(max(cap, 1), dtype=ENTRY_DTYPE)
+    nout, dec, used = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint32()
+    rc = lib().pss_frequent_run(ctx.handle, ptr, n, k, chunks, kind, out.ctypes.data_as(ctypes.c_void_p), cap,
+                                ctypes.byref(nout), ctypes.byref(dec), ctypes.byref(used),
+                                ctypes.c_void_p(_stream(stream)))
+    _check(rc, "pss_frequent_run", int(nout.value))
+    return out[: min(int(nout.value), cap)].copy(), int(dec.value), int(used.value)
+
+
+def pss_frequent_block_summaries(ctx: Context, d_items, k: int, chunks: int, sel, stream=None,
+                                 n: int | None = None):
+    """Frequent summaries of the blocks listed in sel: list of (entries, D)."""
+    ptr, numel = _items(d_items)
+    n = numel if n is None else n
+    sel = np.ascontiguousarray(np.asarray(sel, dtype=np.uint32))
+    out = np.zeros(max(len(sel) * k, 1), dtype=ENTRY_DTYPE)
+    sizes = np.zeros(max(len(sel), 1), dtype=np.uint32)
+    decs = np.zeros(max(len(sel), 1), dtype=np.uint64)
+    rc = lib().pss_frequent_block_summaries(ctx.handle, ptr, n, k, chunks,
+                                            sel.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), len(sel),
+                                            out.ctypes.data_as(ctypes.c_void_p),
+                                            sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                            decs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                            ctypes.c_void_p(_stream(stream)))
+    _check(rc, "pss_frequent_block_summaries")
+    return [(out[i * k: i * k + int(sizes[i])].copy(), int(decs[i])) for i in range(len(sel))]
 
 
 def pss_test_fold_failed_block(s: Summary, n: int, stream=None):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpss.so")
-SOURCES = ["chunk_summary.hip", "combine.hip", "extract.hip", "libpss.hip", "batch.hip", "serve.hip", "noalloc.hip"]
+SOURCES = ["chunk_summary.hip", "combine.hip", "extract.hip", "libpss.hip", "batch.hip", "serve.hip", "noalloc.hip", "readbw.hip", "frequent.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -172,6 +172,31 @@ hipError_t launch_root_extract(const BlockSummaries& v, uint32_t k, uint64_t N, 
     return hipGetLastError();
 }
 
+// Frequent report from the root: (count + D) * k > N is count > floor(N/k) - D,
+// the threshold of a stream of max(0, floor(N/k) - D) * k items; errors are 0,
+// so the canonical order is count descending, item ascending.
+__global__ __launch_bounds__(kExtractThreads) void frequent_report_kernel(BlockSummaries v, uint32_t k, uint64_t N,
+                                                                          int kind, uint32_t cap, DevEntry* out,
+                                                                          uint32_t* out_count) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* small = (uint32_t*)(smem + extract_big_bytes(k));
+    const uint64_t d = v.min[0];
+    const uint64_t q = N / k;
+    const uint64_t n_eff = q > d ? (q - d) * k : 0;
+    extract_body<uint32_t>(v.item, v.cnt, v.err, v.size[0], k, n_eff, kind, cap, out, out_count, smem, small);
+    if (threadIdx.x == 0) *(uint64_t*)(out_count + 2) = d;
+}
+
+hipError_t launch_frequent_report(const BlockSummaries& v, uint32_t k, uint64_t N, int kind, uint32_t cap,
+                                  DevEntry* out, uint32_t* out_count, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
+    const uint32_t lds = extract_lds_bytes(k);
+    hipFuncSetAttribute((const void*)frequent_report_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(frequent_report_kernel, dim3(1), dim3(kExtractThreads), lds, stream, v, k, N, kind, cap, out,
+                       out_count);
+    return hipGetLastError();
+}
+
 // Served queries: one workgroup per query on a persistent summary of the
 // pool (u64 counts), kind and cap per query.
 __global__ __launch_bounds__(kExtractThreads) void serve_query_kernel(const ServeQuery* __restrict__ q,

@@ -336,6 +336,65 @@ uint32_t pss_plan_chunks(const pss_ctx* ctx, uint64_t n, uint32_t k) {
     return pss::plan_chunks(ctx->cu_count, ctx->lds_per_cu, ctx->lds_max, n, k);
 }
 
+int pss_tune_chunks(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, void* stream,
+                    uint32_t* best_chunks, double* best_ms) {
+    if (!ctx || !d_items || !best_chunks) return PSS_EINVAL;
+    if (k < 2) return PSS_EINVAL;
+    if (!k_fits(ctx, k) || n == 0 || n >= kStreamBound) return PSS_ERANGE;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const KPlan kp = kplan(ctx, k);
+    const uint32_t base = pss_plan_chunks(ctx, n, k);
+    std::vector<uint32_t> cand;
+    for (uint64_t c : {(uint64_t)base / 4, (uint64_t)base / 2, (uint64_t)base, (uint64_t)2 * base}) {
+        c = std::max<uint64_t>(1, std::min<uint64_t>({c, (uint64_t)kMaxChunks, n}));
+        if (std::find(cand.begin(), cand.end(), (uint32_t)c) == cand.end()) cand.push_back((uint32_t)c);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return PSS_EDEVICE;
+    }
+    uint32_t best = base;
+    float best_t = -1.f;
+    int rc = PSS_OK;
+    for (uint32_t C : cand) {
+        // the block summaries and the tree: the steps whose cost depends on C
+        unsigned char* cs = nullptr;
+        uint32_t slabs = 0;
+        if (!kp.comb_lds && C > 1) {
+            slabs = std::min(combine_slabs(ctx), C / 2);
+            rc = ctx_grow(ctx, ctx->cscratch, (size_t)slabs * combine_scratch_bytes(k, false));
+            if (rc != PSS_OK) break;
+            cs = (unsigned char*)ctx->cscratch.ptr;
+        }
+        float t_min = -1.f;
+        for (int rep = 0; rep < 3 && rc == PSS_OK; ++rep) {  // the first is a warm-up
+            BlockSummaries b;
+            if (hipEventRecord(e0, st) != hipSuccess) rc = PSS_EDEVICE;
+            if (rc == PSS_OK) rc = run_blocks(ctx, kp, d_items, n, C, st, &b);
+            for (uint32_t step = 1; rc == PSS_OK && step < C; step <<= 1)
+                rc = check(launch_combine_level(b, k, C, step, kp.comb_lds, cs, slabs, st));
+            float t = 0.f;
+            if (rc == PSS_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+                rc = PSS_EDEVICE;
+            if (rc == PSS_OK && rep > 0 && (t_min < 0.f || t < t_min)) t_min = t;
+        }
+        if (rc != PSS_OK) break;
+        if (best_t < 0.f || t_min < best_t) {
+            best_t = t_min;
+            best = C;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != PSS_OK) return rc;
+    *best_chunks = best;
+    if (best_ms) *best_ms = best_t;
+    return PSS_OK;
+}
+
 int pss_create(pss_ctx* ctx, uint32_t k, pss_summary** out) {
     if (!ctx || !out) return PSS_EINVAL;
     *out = nullptr;
@@ -495,6 +554,119 @@ int pss_run(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint3
     rc = pss_update(s, d_items, n, chunks, stream, chunks_used);
     if (rc != PSS_OK) return rc;
     return pss_query(s, PSS_Q_MAJORITY, h_out, cap, n_out, nullptr, stream);
+}
+
+// ---- Frequent (Misra-Gries) in the same pipeline ----
+
+namespace {
+
+// Largest k of the Frequent path on this context: block state, merge and
+// report all in LDS.
+bool frequent_k_fits(const pss_ctx* ctx, uint32_t k) {
+    return k >= 2 && k <= kMaxK && FreqLayout::make(k).lds_bytes <= ctx->lds_max &&
+           frequent_merge_lds_bytes(k) <= ctx->lds_max && extract_lds_bytes(k) <= ctx->lds_max;
+}
+
+int frequent_blocks(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks, hipStream_t st,
+                    BlockSummaries* out) {
+    int rc = ctx_grow(ctx, ctx->blocks, blocks_bytes(chunks, k));
+    if (rc != PSS_OK) return rc;
+    *out = carve_blocks(ctx->blocks.ptr, chunks, k);
+    return check(launch_frequent_blocks(d_items, n, chunks, FreqLayout::make(k), *out, st));
+}
+
+}  // namespace
+
+uint32_t pss_frequent_max_k(const pss_ctx* ctx) {
+    if (!ctx) return 0;
+    uint32_t lo = 2, hi = kMaxK;
+    if (!frequent_k_fits(ctx, lo)) return 0;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (frequent_k_fits(ctx, mid)) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+int pss_frequent_run(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks, int kind,
+                     pss_entry* h_out, uint32_t cap, uint32_t* n_out, uint64_t* h_decrements, uint32_t* chunks_used,
+                     void* stream) {
+    if (!ctx || !d_items || !n_out || (cap > 0 && !h_out)) return PSS_EINVAL;
+    if (kind != PSS_Q_MAJORITY && kind != PSS_Q_TOPK) return PSS_EINVAL;
+    if (k < 2 || (uint64_t)k > n || n >= kStreamBound) return PSS_ERANGE;
+    if (!frequent_k_fits(ctx, k)) return PSS_ERANGE;
+    const uint32_t C = chunks ? chunks : pss_plan_chunks(ctx, n, k);
+    if (C > kMaxChunks) return PSS_ERANGE;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t qbytes = 256 + (size_t)k * sizeof(DevEntry);
+    int rc = ctx_grow(ctx, ctx->query, qbytes);
+    if (rc != PSS_OK) return rc;
+    rc = ensure_pinned(ctx, qbytes);
+    if (rc != PSS_OK) return rc;
+    BlockSummaries b;
+    rc = frequent_blocks(ctx, d_items, n, k, C, st, &b);
+    for (uint32_t step = 1; rc == PSS_OK && step < C; step <<= 1) rc = check(launch_frequent_level(b, k, C, step, st));
+    if (rc != PSS_OK) return rc;
+    uint32_t* d_count = (uint32_t*)ctx->query.ptr;
+    DevEntry* d_ent = (DevEntry*)((char*)ctx->query.ptr + 256);
+    const uint32_t dev_cap = kind == PSS_Q_TOPK ? std::min(cap, k) : k;
+    rc = check(launch_frequent_report(b, k, n, kind, dev_cap, d_ent, d_count, st));
+    if (rc != PSS_OK) return rc;
+    if (hipMemcpyAsync(ctx->pinned, ctx->query.ptr, qbytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return PSS_EDEVICE;
+    const uint32_t q = ((const uint32_t*)ctx->pinned)[0];
+    if (q > k) return PSS_EDEVICE;  // a kernel reported a failed invariant
+    if (h_decrements) *h_decrements = ((const uint64_t*)ctx->pinned)[1];
+    if (chunks_used) *chunks_used = C;
+    *n_out = q;
+    if (kind == PSS_Q_MAJORITY && q > cap) return PSS_ETRUNC;
+    const uint32_t w = std::min(q, cap);
+    if (w) memcpy(h_out, (const char*)ctx->pinned + 256, (size_t)w * sizeof(pss_entry));
+    return PSS_OK;
+}
+
+int pss_frequent_block_summaries(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks,
+                                 const uint32_t* h_sel, uint32_t nsel, pss_entry* h_out, uint32_t* h_sizes,
+                                 uint64_t* h_decrements, void* stream) {
+    if (!ctx || (n > 0 && !d_items) || chunks == 0 ||
+        (nsel > 0 && (!h_sel || !h_out || !h_sizes || !h_decrements)))
+        return PSS_EINVAL;
+    if (k < 2) return PSS_EINVAL;
+    if (!frequent_k_fits(ctx, k) || n >= kStreamBound || chunks > kMaxChunks) return PSS_ERANGE;
+    for (uint32_t i = 0; i < nsel; ++i)
+        if (h_sel[i] >= chunks) return PSS_EINVAL;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    BlockSummaries b;
+    int rc = frequent_blocks(ctx, d_items, n, k, chunks, st, &b);
+    if (rc != PSS_OK) return rc;
+    if (hipStreamSynchronize(st) != hipSuccess) return PSS_EDEVICE;
+    for (uint32_t i = 0; i < nsel; ++i) {
+        const uint32_t c = h_sel[i];
+        uint32_t sz = 0, d = 0;
+        if (hipMemcpy(&sz, b.size + c, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(&d, b.min + c, 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return PSS_EDEVICE;
+        if (sz >= k) return PSS_EDEVICE;
+        h_sizes[i] = sz;
+        h_decrements[i] = d;
+        if (sz == 0) continue;
+        std::vector<uint32_t> tmp(2 * (size_t)sz);
+        const size_t off = (size_t)c * k;
+        if (hipMemcpy(tmp.data(), b.item + off, 4 * (size_t)sz, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(tmp.data() + sz, b.cnt + off, 4 * (size_t)sz, hipMemcpyDeviceToHost) != hipSuccess)
+            return PSS_EDEVICE;
+        pss_entry* o = h_out + (size_t)i * k;
+        for (uint32_t e = 0; e < sz; ++e) {
+            o[e].item = tmp[e];
+            o[e].reserved = 0;
+            o[e].count = tmp[sz + e];
+            o[e].error = 0;
+        }
+    }
+    return PSS_OK;
 }
 
 int pss_test_fold_failed_block(pss_summary* s, uint64_t n, void* stream) {

@@ -152,6 +152,21 @@ size_t extract_scratch_bytes(uint32_t k);
 hipError_t launch_root_extract(const BlockSummaries& v, uint32_t k, uint64_t N, uint32_t cap, DevEntry* out,
                                uint32_t* out_count, hipStream_t stream);
 
+// ---- Frequent (Misra-Gries) summaries: block summaries at stride k with
+// k - 1 counters each, size[] and, in min[], the decrement steps D ----
+hipError_t launch_frequent_blocks(const uint32_t* d_items, uint64_t n, uint32_t chunks, const FreqLayout& L,
+                                  const BlockSummaries& out, hipStream_t stream);
+// One tree level: node j merges summaries 2*step*j and 2*step*j + step.
+hipError_t launch_frequent_level(const BlockSummaries& v, uint32_t k, uint32_t count, uint32_t step,
+                                 hipStream_t stream);
+uint32_t frequent_merge_lds_bytes(uint32_t k);
+// Report of the root (summary 0) for a stream of N items: kind 0 = entries
+// with (count + D) * k > N, kind 1 = the first cap; canonical order (count
+// desc, item asc).  out_count[0] = the count before truncation (0xFFFFFFFF
+// for a failed block), out_count[2..3] = D.
+hipError_t launch_frequent_report(const BlockSummaries& v, uint32_t k, uint64_t N, int kind, uint32_t cap,
+                                  DevEntry* out, uint32_t* out_count, hipStream_t stream);
+
 // Set a wide summary to the empty summary (N = 0, fault cleared).
 hipError_t launch_reset(const WideSummary& s, hipStream_t stream);
 

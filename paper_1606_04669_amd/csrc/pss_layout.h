@@ -135,4 +135,29 @@ struct ChunkLayout {
     PSS_HD bool fits_lds_indices() const { return slots <= kMaxLdsTableSlots && k <= 65535u; }
 };
 
+// Layout of one Frequent block (k - 1 counters for the k-majority problem):
+// the same two-choice hash table as ChunkLayout (slots sized for k), then the
+// input ring; all in LDS.
+struct FreqLayout {
+    uint32_t k, counters;
+    uint32_t nbuckets, tsize, slots;
+    uint32_t off_table, off_ring, lds_bytes;
+
+    PSS_HD static FreqLayout make(uint32_t k) {
+        FreqLayout L;
+        L.k = k;
+        L.counters = k - 1;
+        uint32_t want = (uint32_t)(((uint64_t)k * ChunkLayout::default_slots_x16(k) + 15) / 16);
+        if (want < 256) want = 256;
+        L.nbuckets = (want + kBucketSlots - 1) / kBucketSlots;
+        L.tsize = kBucketSlots * L.nbuckets;
+        L.slots = L.tsize + kStash;
+        uint32_t o = 0;
+        L.off_table = o; o = align16(o + 8 * L.slots);
+        L.off_ring = o;  o = align16(o + 4 * kRing);
+        L.lds_bytes = o;
+        return L;
+    }
+};
+
 }  // namespace pss

@@ -36,15 +36,17 @@ def kernel_source_digest() -> str:
     import hashlib
     h = hashlib.sha256()
     for f in (KERNEL_SOURCE, os.path.join(os.path.dirname(KERNEL_SOURCE), "pss_layout.h"),
-              os.path.join(os.path.dirname(KERNEL_SOURCE), "pss_device.h")):
+              os.path.join(os.path.dirname(KERNEL_SOURCE), "pss_device.h"),
+              os.path.join(os.path.dirname(KERNEL_SOURCE), "pss_table.h")):
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, n_log2: int):
-    """Bytes per block-kernel launch from the committed counter runs, or None
-    when they were taken on another kernel source or workload."""
+def measured_traffic(workload: str, n_log2: int, k: int):
+    """HBM bytes per launch of the block kernel's instance for k, from the
+    committed counter runs, or None when they were taken on another kernel
+    source or workload."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -54,7 +56,7 @@ def measured_traffic(workload: str, n_log2: int):
         return None
     if t.get("workload") != workload or t.get("n_log2") != n_log2:
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_launch_by_k", {}).get(str(k))
 
 
 def copy_calibration(log2_elems: int = 28, reps: int = 3):
@@ -85,26 +87,70 @@ def workload_cases(name: str, n_log2: int, seed: int):
     raise SystemExit("unknown workload %s" % name)
 
 
-def cpu_baseline(streams, ks, host, chunks_of, sample_log2: int):
-    """The oracle, single-threaded, on the first 2^sample_log2 items of every case."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Worker threads for the threaded oracle: the CPUs this process may run
+    on, at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(streams, ks, host, chunks_of, sample_log2: int, threads_sample_log2: int):
+    """The oracle on the GPU host's CPU: single-threaded on the first
+    2^sample_log2 items of every case, and in its T-thread form (chunk
+    summaries on T threads with the same sequential function, the fixed tree
+    on one thread: the paper's shared-memory shape) on the first
+    2^threads_sample_log2 items."""
     import oracle
-    s = 1 << sample_log2
-    total_items, total_s = 0, 0.0
-    for st, a in zip(streams, host):
-        for k in ks:
-            n = len(a)
-            c = max(1, round(chunks_of[(st.name, k)] * s / n))
-            t = time.perf_counter()
-            oracle.run(a[:s], k, c)
-            total_s += time.perf_counter() - t
-            total_items += s
+
+    def leg(sample, threads):
+        total_items, total_s = 0, 0.0
+        for st, a in zip(streams, host):
+            for k in ks:
+                n = len(a)
+                s_n = min(sample, n)
+                c = max(1, round(chunks_of[(st.name, k)] * s_n / n))
+                t = time.perf_counter()
+                if threads == 1:
+                    oracle.run(a[:s_n], k, c)
+                else:
+                    oracle.run_threads(a[:s_n], k, c, threads)
+                total_s += time.perf_counter() - t
+                total_items += s_n
+        return total_items / total_s / 1e9, total_s
+
+    T = host_threads()
+    v1, s1 = leg(1 << sample_log2, 1)
+    log("cpu baseline: single thread %.4f G items/s" % v1)
+    vT, sT = leg(1 << threads_sample_log2, T)
+    log("cpu baseline: %d threads %.4f G items/s" % (T, vT))
+    ncases = len(streams) * len(ks)
     return {
-        "value": total_items / total_s / 1e9,
+        "value": round(vT, 4),
         "unit": "G items/s",
-        "cores": 1,
+        "cores": T,
         "kind": "oracle",
-        "sample": "first 2^%d items of each of the %d cases (same k, chunk count scaled to the sample), "
-                  "single-threaded C oracle; %.1f s of CPU work" % (sample_log2, len(streams) * len(ks), total_s),
+        "sample": "first 2^%d items of each of the %d cases (same k, chunk count scaled to the sample); the C "
+                  "oracle with its chunk summaries on %d threads and the fixed tree on one; %.1f s of CPU work"
+                  % (threads_sample_log2, ncases, T, sT),
+        "cpu_model": cpu_model(),
+        "nproc": os.cpu_count(),
+        "single_thread": {"value": round(v1, 4), "unit": "G items/s", "cores": 1,
+                          "sample": "first 2^%d items of each case, single-threaded C oracle; %.1f s of CPU work"
+                                    % (sample_log2, s1)},
     }
 
 
@@ -274,6 +320,185 @@ def served_leg(B, ctx, seed: int, nrequests: int, loads):
     }
 
 
+def run_cases(B, ctx, streams, dev, ks, chunks_of, steps, warmup, stream):
+    """Warm-up, then `steps` timed passes over every (stream, k) case.
+    Returns (wall seconds of the timed passes, per-case wall ms lists,
+    per-case phase ms sums, per-case launch counts)."""
+    import torch
+    for i in range(warmup):
+        for st, d in zip(streams, dev):
+            for k in ks:
+                B.pss_run(ctx, d, k=k, chunks=chunks_of[(st.name, k)], stream=stream)
+        log("warmup %d done" % i)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.phase_times(reset=True)
+    wall, phase, nlaunch = {}, {}, {}
+    t0 = time.perf_counter()
+    for i in range(steps):
+        for st, d in zip(streams, dev):
+            for k in ks:
+                key = (st.name, k)
+                tc = time.perf_counter()
+                B.pss_run(ctx, d, k=k, chunks=chunks_of[key], stream=stream)  # blocks: its report is on the host
+                wall.setdefault(key, []).append((time.perf_counter() - tc) * 1e3)
+                ms, nl = ctx.phase_times(reset=True)  # HIP events the library recorded on `stream`
+                acc = phase.setdefault(key, [0.0] * 4)
+                cnt = nlaunch.setdefault(key, [0] * 4)
+                for j in range(4):
+                    acc[j] += ms[j]
+                    cnt[j] += nl[j]
+        log("step %d done" % i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.timing(False)
+    return elapsed, wall, phase, nlaunch
+
+
+def roofline_of(streams, ks, n_items, phase, nlaunch, peak, measured):
+    """Block-kernel read roofline: per case, per k (one kernel instance per
+    k class), and for the instance that takes the most GPU time."""
+    per_case, per_k = [], {}
+    for st in streams:
+        for k in ks:
+            ms, nl = phase[(st.name, k)][0], max(1, nlaunch[(st.name, k)][0])
+            avg = ms / nl
+            gbs = 4.0 * n_items / (avg * 1e-3) / 1e9
+            per_case.append({"stream": st.name, "k": k, "kernel_ms": round(avg, 4), "achieved_gbs": round(gbs, 1),
+                             "frac": round(gbs / peak, 4)})
+            t = per_k.setdefault(k, [0.0, 0])
+            t[0] += ms
+            t[1] += nl
+    inst = []
+    for k, (ms, nl) in per_k.items():
+        avg = ms / max(1, nl)
+        gbs = 4.0 * n_items / (avg * 1e-3) / 1e9
+        inst.append({"k": k, "gpu_ms": ms, "avg_launch_ms": round(avg, 4), "launches": nl, "achieved": round(gbs, 1)})
+    dom = max(inst, key=lambda r: r["gpu_ms"])
+    all_ms = sum(r["gpu_ms"] for r in inst)
+    all_n = sum(r["launches"] for r in inst)
+    blend = 4.0 * n_items / (all_ms / max(1, all_n) * 1e-3) / 1e9
+    return dom, inst, per_case, blend
+
+
+def highk_leg(B, ctx, seed: int, steps: int, warmup: int):
+    """The high-k workload: n = 2^31 (Zipf 1.1 over 2^32 hashed ids and the
+    adversarial round-robin stream with a planted 5% item), k in {10^4,
+    5 x 10^4}, the planner's chunk count; block state, COMBINE arrays and
+    the report in device memory."""
+    import numpy as np
+    import torch
+    streams, ks = workload_cases("plain-highk", 31, seed)
+    dev = []
+    n = 0
+    for st in streams:
+        t = time.perf_counter()
+        a = st.generate()
+        n = len(a)
+        dev.append(torch.from_numpy(a.view(np.int32)).to("cuda"))
+        del a
+        log("highk: generated %s in %.1fs" % (st.name, time.perf_counter() - t))
+    chunks_of = {(st.name, k): ctx.plan_chunks(n, k) for st in streams for k in ks}
+    stream = torch.cuda.current_stream()
+    elapsed, wall, phase, nlaunch = run_cases(B, ctx, streams, dev, ks, chunks_of, steps, warmup, stream)
+    items = n * len(streams) * len(ks) * steps
+    cases = []
+    for st in streams:
+        for k in ks:
+            key = (st.name, k)
+            t = sorted(wall[key])
+            med = t[len(t) // 2]
+            ph = phase[key]
+            tot = sum(ph)
+            cases.append({"stream": st.name, "k": k, "chunks": chunks_of[key], "ms_median": round(med, 3),
+                          "g_items_per_s": round(n / med / 1e6, 3),
+                          "reduction_share": round((ph[1] + ph[2]) / tot, 4) if tot else None})
+    dom, inst, per_case, _ = roofline_of(streams, ks, n, phase, nlaunch, HBM_PEAK_GBS, None)
+    del dev
+    torch.cuda.empty_cache()
+    return {
+        "workload": "plain-highk: n=2^31 per stream, streams=%s, k=%s, chunks from the planner"
+                    % ([s.name for s in streams], ks),
+        "g_items_per_s": round(items / elapsed / 1e9, 3),
+        "cases": cases,
+        "roofline": {"bound": "hbm", "kernel": "chunk_summary_kernel (state in device memory)",
+                     "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(dom["achieved"] / HBM_PEAK_GBS, 4), "k": dom["k"],
+                     "avg_launch_ms": dom["avg_launch_ms"], "launches": dom["launches"]},
+    }
+
+
+def accuracy_leg(B, ctx, streams, dev, seed: int, ks):
+    """Section 4's accuracy metrics on the plain-large streams and a Zipf 1.1
+    stream of the same length: ARE over the reported items, precision and
+    recall against exact counts (device sort); the planner's chunk count."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1606_04669_amd import accuracy as A
+    n = dev[0].numel()
+    extra = W.plain_large(1.1, seed, n)
+    d11 = torch.from_numpy(extra.generate().view(np.int32)).to("cuda")
+    out = []
+    for st, d in list(zip(streams, dev)) + [(extra, d11)]:
+        ex = A.exact_counts_device(d)
+        for k in ks:
+            C = ctx.plan_chunks(n, k)
+            got, _ = B.pss_run(ctx, d, k=k, chunks=C)
+            m = A.metrics(got, ex, k)
+            if m["recall"] != 1.0:
+                raise RuntimeError("recall below 100%% on %s k=%d: %s" % (st.name, k, m))
+            m.update({"stream": st.name, "chunks": C, "are": float("%.4g" % m["are"]),
+                      "max_rel_error": float("%.4g" % m["max_rel_error"]), "precision": round(m["precision"], 4)})
+            out.append(m)
+        del ex
+        log("accuracy: %s done" % st.name)
+    del d11
+    torch.cuda.empty_cache()
+    return {"metric": "ARE over the reported items (|f - f^| / f), precision, recall vs exact counts",
+            "n": n, "cases": out}
+
+
+def sweep_leg(B, ctx, seed: int, n_log2: int, ks, reps: int):
+    """Fractional overhead and accuracy against the chunk count: for Zipf 1.1
+    and 1.8 streams, each k and C in {P/4, P, 4P} (P the planner's count):
+    wall ms of the whole path, the reduction's share of GPU time (tree and
+    fold over all phases: the paper's fractional overhead), and ARE."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1606_04669_amd import accuracy as A
+    n = 1 << n_log2
+    rows = []
+    for alpha in (1.1, 1.8):
+        d = torch.from_numpy(W.plain_large(alpha, seed, n).generate().view(np.int32)).to("cuda")
+        ex = A.exact_counts_device(d)
+        for k in ks:
+            P = ctx.plan_chunks(n, k)
+            for C in sorted({max(1, P // 4), P, 4 * P}):
+                got, _ = B.pss_run(ctx, d, k=k, chunks=C)  # warm-up (allocates)
+                ctx.timing(True)
+                ctx.phase_times(reset=True)
+                wall = []
+                for _ in range(reps):
+                    t = time.perf_counter()
+                    got, _ = B.pss_run(ctx, d, k=k, chunks=C)
+                    wall.append((time.perf_counter() - t) * 1e3)
+                ms, _nl = ctx.phase_times(reset=True)
+                ctx.timing(False)
+                tot = sum(ms)
+                m = A.metrics(got, ex, k)
+                rows.append({"alpha": alpha, "k": k, "chunks": C, "planner": P, "ms": round(sorted(wall)[reps // 2], 3),
+                             "block_ms": round(ms[0] / reps, 3), "tree_ms": round(ms[1] / reps, 3),
+                             "reduction_share": round((ms[1] + ms[2]) / tot, 4) if tot else None,
+                             "are": float("%.4g" % m["are"]), "precision": round(m["precision"], 4),
+                             "recall": m["recall"]})
+        del d, ex
+        torch.cuda.empty_cache()
+        log("sweep: alpha %.1f done" % alpha)
+    return {"n": n, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,10 +507,16 @@ def main():
     ap.add_argument("--workload", default="plain-large", choices=["plain-large", "plain", "plain-highk"])
     ap.add_argument("--n-log2", type=int, default=None)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--chunks", default="tuned", choices=["tuned", "planner"],
+                    help="chunk count per case: the library's autotuner (pss_tune_chunks) or its planner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=24)
+    ap.add_argument("--cpu-threads-sample-log2", type=int, default=26)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served leg")
+    ap.add_argument("--no-highk", action="store_true", help="skip the high-k leg")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy leg")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the k x chunk-count sweep")
     ap.add_argument("--served-requests", type=int, default=4000)
     ap.add_argument("--served-loads", default="2000,10000,40000,0",
                     help="offered loads in requests/s (0: all at once)")
@@ -318,50 +549,39 @@ def main():
         dev.append(torch.from_numpy(a.view(np.int32)).to("cuda"))
     torch.cuda.synchronize()
     ctx = B.Context(0)
-    chunks_of = {(st.name, k): ctx.plan_chunks(len(a), k) for st, a in zip(streams, host) for k in ks}
     stream = torch.cuda.current_stream()
+    chunks_of, tuned_ms = {}, {}
+    for st, a, d in zip(streams, host, dev):
+        for k in ks:
+            if args.chunks == "tuned":
+                c, tms = ctx.tune_chunks(d, k, stream=stream)
+                chunks_of[(st.name, k)], tuned_ms[(st.name, k)] = c, tms
+            else:
+                chunks_of[(st.name, k)] = ctx.plan_chunks(len(a), k)
+    if args.chunks == "tuned":
+        log("autotuned chunk counts: %s" % {"%s/k=%d" % key: v for key, v in chunks_of.items()})
+    read_gbs = ctx.read_bandwidth(dev[0])
+    log("read bandwidth over a %d-byte stream: %.1f GB/s" % (dev[0].numel() * 4, read_gbs))
 
-    def step():
-        out = {}
-        for st, d in zip(streams, dev):
-            for k in ks:
-                got, used = B.pss_run(ctx, d, k=k, chunks=chunks_of[(st.name, k)], stream=stream)
-                out[(st.name, k)] = len(got)
-        return out
-
-    for i in range(args.warmup):
-        step()
-        log("warmup %d done" % i)
-    torch.cuda.synchronize()
-    ctx.timing(True)
-    ctx.phase_times(reset=True)
-    per_case_ms = {}
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        for st, d in zip(streams, dev):
-            for k in ks:
-                tc = time.perf_counter()
-                B.pss_run(ctx, d, k=k, chunks=chunks_of[(st.name, k)], stream=stream)
-                per_case_ms.setdefault((st.name, k), []).append((time.perf_counter() - tc) * 1e3)
-        log("step %d done" % i)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms, launches = ctx.phase_times(reset=True)
-    ctx.timing(False)
-
+    elapsed, wall, phase, nlaunch = run_cases(B, ctx, streams, dev, ks, chunks_of, args.steps, args.warmup, stream)
     items_per_step = sum(len(a) for a in host) * len(ks)
     value = items_per_step * args.steps / elapsed / 1e9
     n_items = len(host[0])
-    cs_avg_ms = ms[0] / max(1, launches[0])
-    achieved = 4.0 * n_items / (cs_avg_ms * 1e-3) / 1e9  # algorithmic bytes: 4 B per item
+    dom, inst, per_case, blend = roofline_of(streams, ks, n_items, phase, nlaunch, HBM_PEAK_GBS, read_gbs)
     cases = []
     for st in streams:
         for k in ks:
-            t = sorted(per_case_ms[(st.name, k)])
+            key = (st.name, k)
+            t = sorted(wall[key])
             med = t[len(t) // 2]
-            cases.append({"stream": st.name, "k": k, "chunks": chunks_of[(st.name, k)],
-                          "ms_median": round(med, 3), "g_items_per_s": round(n_items / med / 1e6, 2)})
+            c = {"stream": st.name, "k": k, "chunks": chunks_of[key], "ms_median": round(med, 3),
+                 "g_items_per_s": round(n_items / med / 1e6, 2)}
+            if key in tuned_ms:
+                c["tuned_blocks_tree_ms"] = round(tuned_ms[key], 3)
+            cases.append(c)
+    ms = [sum(phase[key][j] for key in phase) for j in range(4)]
     total_ms = sum(ms)
+    dom_launch_ms = dom["avg_launch_ms"]
     result = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -376,21 +596,29 @@ def main():
         "dtype": "u32",
         "data": "synthetic (seeded Zipf/uniform uint32 streams, resident in HBM)",
         "config": {
-            "workload": "%s: n=2^%d per stream, streams=%s, k=%s, chunks from the planner" % (
-                args.workload, n_log2, [s.name for s in streams], ks),
+            "workload": "%s: n=2^%d per stream, streams=%s, k=%s, chunks %s" % (
+                args.workload, n_log2, [s.name for s in streams], ks,
+                "from the autotuner (pss_tune_chunks), recorded per case" if args.chunks == "tuned"
+                else "from the planner"),
             "n": n_items,
             "cases": cases,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "chunk_summary_kernel",
-            "achieved": round(achieved, 1),
+            "kernel": "chunk_summary_kernel, k=%d instance (the most GPU time)" % dom["k"],
+            "achieved": dom["achieved"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(args.workload, n_log2),
-            "avg_launch_ms": round(cs_avg_ms, 4),
-            "launches": launches[0],
+            "frac": round(dom["achieved"] / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(args.workload, n_log2, dom["k"]),
+            "avg_launch_ms": dom_launch_ms,
+            "launches": dom["launches"],
+            "measured_read_gbs": round(read_gbs, 1),
+            "frac_of_measured_read": round(dom["achieved"] / read_gbs, 4),
+            "by_k": [{"k": r["k"], "achieved": r["achieved"], "frac": round(r["achieved"] / HBM_PEAK_GBS, 4),
+                      "avg_launch_ms": r["avg_launch_ms"], "launches": r["launches"]} for r in inst],
+            "all_launches_achieved": round(blend, 1),
+            "per_case": per_case,
         },
         "phases_ms_per_step": {
             "chunk_summary": round(ms[0] / args.steps, 3),
@@ -400,16 +628,23 @@ def main():
             "reduction_share": round((ms[1] + ms[2]) / total_ms, 4) if total_ms else None,
         },
     }
+    if args.workload == "plain-large" and not args.no_accuracy:
+        result["accuracy"] = accuracy_leg(B, ctx, streams, dev, args.seed, [500, 1000, 2000, 4000, 8000])
+    del dev
+    torch.cuda.empty_cache()
+    if args.workload == "plain-large" and not args.no_sweep:
+        result["sweep"] = sweep_leg(B, ctx, args.seed, n_log2, [500, 2000, 8000], 3)
+    if args.workload == "plain-large" and not args.no_highk:
+        result["highk"] = highk_leg(B, ctx, args.seed, 2, 1)
     if not args.no_batched:
-        del dev
-        torch.cuda.empty_cache()
         result["batched"] = batched_leg(B, ctx, args.seed, args.batched_replays, args.batched_streams)
     if not args.no_served:
         result["served"] = served_leg(B, ctx, args.seed, args.served_requests,
                                       [float(x) for x in args.served_loads.split(",")])
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a sample")
-        result["cpu_baseline"] = cpu_baseline(streams, ks, host, chunks_of, args.cpu_sample_log2)
+        log("timing the CPU oracle on samples")
+        result["cpu_baseline"] = cpu_baseline(streams, ks, host, chunks_of, args.cpu_sample_log2,
+                                              args.cpu_threads_sample_log2)
     print(json.dumps(result), flush=True)
     ctx.close()
 

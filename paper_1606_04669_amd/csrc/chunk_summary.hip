@@ -636,7 +636,9 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
     uint32_t* ring = (uint32_t*)(lds + L.off_ring);
     const uint4* stash4 = tbl4 + T / 2;
 
-    for (uint32_t i = lane; i < S; i += kWave) table[i] = 0ull;
+    const uint32_t ekey = uniform(empty_key_e1(NB, hk));  // key of empty slots in buckets 0 and 1
+    if (ekey == 0u) return kOverflow;  // unusable hash functions: the caller tries others
+    for (uint32_t i = lane; i < S; i += kWave) table[i] = empty_entry(ekey, i);
 
     // Wave-uniform state.  Every update goes through uniform() so the compiler
     // keeps it in scalar registers and every loop that contains wave-wide
@@ -698,7 +700,9 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
                     const uint32_t dst = __builtin_popcount(e1) >= __builtin_popcount(e2)
                                              ? kBucketSlots * s1 + (uint32_t)__builtin_ctz(e1)
                                              : kBucketSlots * s2 + (uint32_t)__builtin_ctz(e2);
-                    if (atomicCAS((unsigned long long*)&table[dst], 0ull, (unsigned long long)e) == 0ull) {
+                    const uint64_t emp = empty_entry(ekey, dst);
+                    if (atomicCAS((unsigned long long*)&table[dst], (unsigned long long)emp, (unsigned long long)e) ==
+                        emp) {
                         errs[dst] = errs[T + lane];
                         table[T + lane] = 0ull;
                         moved = true;
@@ -817,9 +821,10 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
                     break;
                 }
                 if (!join) {
+                    const uint64_t emp = empty_entry(ekey, h);
                     const uint64_t old =
-                        atomicCAS((unsigned long long*)&table[h], 0ull, (unsigned long long)mine);
-                    if (old == 0ull) {
+                        atomicCAS((unsigned long long*)&table[h], (unsigned long long)emp, (unsigned long long)mine);
+                    if (old == emp) {
                         hp = h;
                         break;
                     }
@@ -952,7 +957,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
         if (full) {
             if (vv) {
                 if (vr < rp)
-                    table[vs] = 0ull;
+                    table[vs] = empty_entry(ekey, vs);
                 else
                     words[2 * vs + 1] = m;
             }
@@ -964,7 +969,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
                 errs[hp] = full ? m : 0u;
                 table[hp] = make_entry(x, full ? m + 1u : 1u);
             } else {
-                table[hp] = 0ull;
+                table[hp] = empty_entry(ekey, hp);
             }
         }
         const bool repeat = in && miss && !newf;

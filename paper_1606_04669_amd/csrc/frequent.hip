@@ -54,7 +54,9 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
     const uint4* stash4 = tbl4 + T / 2;
     uint32_t* ring = (uint32_t*)(lds + L.off_ring);
 
-    for (uint32_t i = lane; i < S; i += kWave) table[i] = 0ull;
+    const uint32_t ekey = uniform(empty_key_e1(NB, hk));  // key of empty slots in buckets 0 and 1
+    if (ekey == 0u) return kFqOverflow;  // unusable hash functions: the caller tries others
+    for (uint32_t i = lane; i < S; i += kWave) table[i] = empty_entry(ekey, i);
 
     // wave-uniform state (readfirstlane-anchored, see the Space Saving kernel)
     uint32_t size = 0, dec = 0, failed = 0, stash_live = 0;
@@ -95,7 +97,9 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
                     const uint32_t dst = __builtin_popcount(e1) >= __builtin_popcount(e2)
                                              ? kBucketSlots * s1 + (uint32_t)__builtin_ctz(e1)
                                              : kBucketSlots * s2 + (uint32_t)__builtin_ctz(e2);
-                    if (atomicCAS((unsigned long long*)&table[dst], 0ull, (unsigned long long)e) == 0ull) {
+                    const uint64_t emp = empty_entry(ekey, dst);
+                    if (atomicCAS((unsigned long long*)&table[dst], (unsigned long long)emp, (unsigned long long)e) ==
+                        emp) {
                         table[T + lane] = 0ull;
                         moved = true;
                     }
@@ -173,8 +177,10 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
                     break;
                 }
                 if (!join) {
-                    const uint64_t old = atomicCAS((unsigned long long*)&table[h], 0ull, (unsigned long long)mine);
-                    if (old == 0ull) {
+                    const uint64_t emp = empty_entry(ekey, h);
+                    const uint64_t old =
+                        atomicCAS((unsigned long long*)&table[h], (unsigned long long)emp, (unsigned long long)mine);
+                    if (old == emp) {
                         hp = h;
                         break;
                     }
@@ -217,7 +223,7 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
         //    with count 1, repeats add 1 to their value's new counter; claims
         //    past the prefix (the dropped item's among them) are released
         if (in && hit) atomicAdd(&words[2 * slot + 1], 1u);
-        if (newf) table[hp] = in ? make_entry(x, 1u) : 0ull;
+        if (newf) table[hp] = in ? make_entry(x, 1u) : empty_entry(ekey, hp);
         const bool repeat = in && miss && !newf;
         if (ballot(repeat)) {
             wave_sync();
@@ -245,7 +251,7 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
                     const uint32_t s = b + j * kWave + lane;
                     if (live_tag(cv[j])) {
                         if (cv[j] == 1u) {
-                            table[s] = 0ull;
+                            table[s] = empty_entry(ekey, s);
                             freed += 1;
                             sfreed += s >= T ? 1u : 0u;
                         } else {

@@ -72,6 +72,30 @@ __device__ __forceinline__ uint32_t alt_bucket(uint32_t x, uint32_t nb, uint32_t
 
 __device__ __forceinline__ bool live_tag(uint32_t tag) { return tag - 1u < kTagVict - 1u; }
 
+// Keys of empty bucket slots.  A lookup compares an item only with the keys
+// of its own two buckets, so an empty slot of bucket b may hold any id whose
+// two buckets both differ from b: no lookup that reads bucket b can match
+// it, and lookups need not test count words.  Id 0 has buckets 0 and 1 under
+// any multipliers (0 times anything is 0, and a second bucket equal to the
+// first moves to its neighbour), so empty slots of every bucket but 0 and 1
+// hold 0, and those of buckets 0 and 1 hold an id e1 whose two buckets are
+// neither.  (Stash slots are compared only while live; they keep 0.)
+//
+// e1 for nb buckets under hk, or 0 when none was found among the first ids
+// (the caller then treats the hash functions as unusable).
+__device__ __forceinline__ uint32_t empty_key_e1(uint32_t nb, const HashKeys& hk) {
+    for (uint32_t e1 = 1u; e1 < 1024u; ++e1) {
+        const uint32_t c = home_bucket(e1, nb, hk), d = alt_bucket(e1, nb, c, hk);
+        if (c > 1u && d > 1u) return e1;
+    }
+    return 0u;
+}
+
+// The entry of an empty slot s.
+__device__ __forceinline__ uint64_t empty_entry(uint32_t e1, uint32_t s) {
+    return s < 2u * kBucketSlots ? (uint64_t)e1 : 0ull;
+}
+
 // One bucket: kBucketSlots key/tag pairs, read with kBucketSlots / 2
 // 16-byte loads.
 constexpr int kBucketQuads = (int)kBucketSlots / 2;
@@ -86,13 +110,15 @@ __device__ __forceinline__ Bucket load_bucket(const uint4* tbl4, uint32_t b) {
     return r;
 }
 
-// Slot masks (bit i = slot i of the bucket).
+// Slot masks (bit i = slot i of the bucket).  At a window's lookups a bucket
+// slot holds a counter or is empty with a key no lookup of that bucket can
+// match (empty_entry), so a matching key is a counter of the item.
 __device__ __forceinline__ uint32_t match_mask(const Bucket& B, uint32_t x) {
     uint32_t m = 0;
 #pragma unroll
     for (int i = 0; i < kBucketQuads; ++i) {
-        m |= ((B.q[i].x == x && live_tag(B.q[i].y)) ? 1u : 0u) << (2 * i);
-        m |= ((B.q[i].z == x && live_tag(B.q[i].w)) ? 1u : 0u) << (2 * i + 1);
+        m |= (B.q[i].x == x ? 1u : 0u) << (2 * i);
+        m |= (B.q[i].z == x ? 1u : 0u) << (2 * i + 1);
     }
     return m;
 }

@@ -499,6 +499,50 @@ def sweep_leg(B, ctx, seed: int, n_log2: int, ks, reps: int):
     return {"n": n, "rows": rows}
 
 
+def frequent_leg(B, ctx, streams, dev, ks, steps: int):
+    """The Frequent (Misra-Gries) summary in the same pipeline on the same
+    streams and k: wall ms per call, G items/s, the block kernel's read
+    roofline (HIP events the library records on the launch stream)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    n = dev[0].numel()
+    cases = []
+    kms = {}
+    for st, d in zip(streams, dev):
+        for k in ks:
+            C = ctx.plan_chunks(n, k)
+            B.pss_frequent_run(ctx, d, k=k, chunks=C, stream=stream)  # warm-up (allocates)
+            ctx.timing(True)
+            ctx.phase_times(reset=True)
+            wall = []
+            for _ in range(steps):
+                t = time.perf_counter()
+                B.pss_frequent_run(ctx, d, k=k, chunks=C, stream=stream)
+                wall.append((time.perf_counter() - t) * 1e3)
+            ms, nl = ctx.phase_times(reset=True)
+            ctx.timing(False)
+            med = sorted(wall)[len(wall) // 2]
+            kern = ms[0] / max(1, nl[0])
+            acc = kms.setdefault(k, [0.0, 0])
+            acc[0] += ms[0]
+            acc[1] += nl[0]
+            cases.append({"stream": st.name, "k": k, "chunks": C, "ms_median": round(med, 3),
+                          "g_items_per_s": round(n / med / 1e6, 2), "block_kernel_ms": round(kern, 4),
+                          "achieved_gbs": round(4.0 * n / (kern * 1e-3) / 1e9, 1) if kern > 0 else None,
+                          "tree_ms": round(ms[1] / max(1, steps), 3)})
+    total_items = n * len(cases) * steps
+    total_s = sum(c["ms_median"] for c in cases) * steps / 1e3
+    dom_k = max(kms, key=lambda k: kms[k][0])
+    dom_ms = kms[dom_k][0] / max(1, kms[dom_k][1])
+    ach = 4.0 * n / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    return {"workload": "the plain-large streams and k with the Frequent summary (k - 1 counters), "
+                        "the planner's chunk count",
+            "g_items_per_s": round(total_items / total_s / 1e9, 3), "cases": cases,
+            "roofline": {"bound": "hbm", "kernel": "frequent_block_kernel, k=%d" % dom_k, "achieved": round(ach, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "avg_launch_ms": round(dom_ms, 4)}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -517,6 +561,7 @@ def main():
     ap.add_argument("--no-highk", action="store_true", help="skip the high-k leg")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy leg")
     ap.add_argument("--no-sweep", action="store_true", help="skip the k x chunk-count sweep")
+    ap.add_argument("--no-frequent", action="store_true", help="skip the Frequent (Misra-Gries) leg")
     ap.add_argument("--served-requests", type=int, default=4000)
     ap.add_argument("--served-loads", default="2000,10000,40000,0",
                     help="offered loads in requests/s (0: all at once)")
@@ -628,6 +673,8 @@ def main():
             "reduction_share": round((ms[1] + ms[2]) / total_ms, 4) if total_ms else None,
         },
     }
+    if args.workload == "plain-large" and not args.no_frequent:
+        result["frequent"] = frequent_leg(B, ctx, streams, dev, ks, 3)
     if args.workload == "plain-large" and not args.no_accuracy:
         result["accuracy"] = accuracy_leg(B, ctx, streams, dev, args.seed, [500, 1000, 2000, 4000, 8000])
     del dev

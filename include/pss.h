@@ -239,7 +239,9 @@ uint32_t pss_frequent_max_k(const pss_ctx* ctx);
  * count descending, item ascending.  *h_decrements (may be NULL) receives
  * the merged summary's D, *chunks_used (may be NULL) C.  Requires
  * 2 <= k <= n < 2^32 - 128 and k <= pss_frequent_max_k() (else PSS_ERANGE).
- * Blocks until the result is on the host; uses the context's workspace. */
+ * Blocks until the result is on the host; uses the context's workspace.
+ * With pss_timing_enable, its phases count as block summaries (0), tree
+ * (1) and report (3) in pss_phase_times. */
 int pss_frequent_run(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, uint32_t chunks, int kind,
                      pss_entry* h_out, uint32_t cap, uint32_t* n_out, uint64_t* h_decrements, uint32_t* chunks_used,
                      void* stream);

@@ -605,17 +605,24 @@ int pss_frequent_run(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t
     rc = ensure_pinned(ctx, qbytes);
     if (rc != PSS_OK) return rc;
     BlockSummaries b;
+    hipEvent_t t0 = mark(ctx, st);
     rc = frequent_blocks(ctx, d_items, n, k, C, st, &b);
+    if (rc != PSS_OK) return rc;
+    close_phase(ctx, 0, t0, st);
+    hipEvent_t t1 = mark(ctx, st);
     for (uint32_t step = 1; rc == PSS_OK && step < C; step <<= 1) rc = check(launch_frequent_level(b, k, C, step, st));
     if (rc != PSS_OK) return rc;
+    close_phase(ctx, 1, t1, st);
     uint32_t* d_count = (uint32_t*)ctx->query.ptr;
     DevEntry* d_ent = (DevEntry*)((char*)ctx->query.ptr + 256);
     const uint32_t dev_cap = kind == PSS_Q_TOPK ? std::min(cap, k) : k;
+    hipEvent_t t3 = mark(ctx, st);
     rc = check(launch_frequent_report(b, k, n, kind, dev_cap, d_ent, d_count, st));
     if (rc != PSS_OK) return rc;
-    if (hipMemcpyAsync(ctx->pinned, ctx->query.ptr, qbytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
+    if (hipMemcpyAsync(ctx->pinned, ctx->query.ptr, qbytes, hipMemcpyDeviceToHost, st) != hipSuccess)
         return PSS_EDEVICE;
+    close_phase(ctx, 3, t3, st);
+    if (hipStreamSynchronize(st) != hipSuccess) return PSS_EDEVICE;
     const uint32_t q = ((const uint32_t*)ctx->pinned)[0];
     if (q > k) return PSS_EDEVICE;  // a kernel reported a failed invariant
     if (h_decrements) *h_decrements = ((const uint64_t*)ctx->pinned)[1];

@@ -76,6 +76,16 @@ __device__ __forceinline__ uint32_t slot_count(const uint32_t* words, uint32_t s
     return live_tag(c) ? c : 0xFFFFFFFFu;
 }
 
+// A count word that other lanes have just changed with atomics: from LDS
+// with an LDS load, from the HBM-resident state with a volatile load.
+template <bool G>
+__device__ __forceinline__ uint32_t tag_word(const uint32_t* words, uint32_t i) {
+    if constexpr (G)
+        return ((const volatile uint32_t*)words)[i];
+    else
+        return lds_reread(words + i);
+}
+
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, uint32_t src) {
     const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, (int)src);
     const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), (int)src);
@@ -917,11 +927,11 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
         KSTAT_ADD(6, KSTAT_NOW() - tv);
         const unsigned long long tq = KSTAT_NOW();
 
-        const uint32_t rep = miss ? (((const volatile uint32_t*)words)[2 * hp + 1] - kTagPend) : lane;
+        const uint32_t rep = miss ? (tag_word<G>(words, 2 * hp + 1) - kTagPend) : lane;
         // a hit on a counter tagged as the j-th victim: jmark = j + 1
         uint32_t jmark = 0;
         if (hit && full) {
-            const uint32_t c = ((const volatile uint32_t*)words)[2 * slot + 1];
+            const uint32_t c = tag_word<G>(words, 2 * slot + 1);
             jmark = (c >= kTagVict && c < kTagPend) ? c - kTagVict + 1u : 0u;
         }
         const uint64_t newmask = ballot(miss && rep == lane);

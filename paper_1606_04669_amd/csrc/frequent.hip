@@ -209,7 +209,7 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
 
         // 3. new items (the lowest lane of each claimed value) in window
         //    order; the one beyond the free counters is a decrement step
-        const uint32_t rep = miss ? (((const volatile uint32_t*)words)[2 * hp + 1] - kTagPend) : lane;
+        const uint32_t rep = miss ? (lds_reread(words + 2 * hp + 1) - kTagPend) : lane;
         const uint64_t newmask = ballot(miss && rep == lane);
         const bool newf = (newmask >> lane) & 1ull;
         const uint32_t nrank = mbcnt(newmask);

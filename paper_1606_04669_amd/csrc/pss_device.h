@@ -30,6 +30,14 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// A word of LDS that lanes of this wave have just changed with atomics,
+// read again from memory.  The access goes through an LDS pointer: a
+// volatile read through a generic pointer becomes a FLAT load, and waiting
+// for a FLAT load also waits for every global load and store in flight.
+__device__ __forceinline__ uint32_t lds_reread(const uint32_t* p) {
+    return *(const volatile __attribute__((address_space(3))) uint32_t*)p;
+}
+
 // DPP lane moves (GFX9 encodings): quad_perm, row mirrors and row broadcasts.
 template <int Ctrl, int RowMask>
 __device__ __forceinline__ uint32_t dpp(uint32_t v) {

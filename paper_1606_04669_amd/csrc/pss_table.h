@@ -99,15 +99,31 @@ __device__ __forceinline__ uint64_t empty_entry(uint32_t e1, uint32_t s) {
 // One bucket: kBucketSlots key/tag pairs, read with kBucketSlots / 2
 // 16-byte loads.
 constexpr int kBucketQuads = (int)kBucketSlots / 2;
+static_assert(kBucketQuads == 4, "the quad rotation below assumes four 16-byte loads per bucket");
+
+// A bucket as one lane read it.  Buckets are 64 bytes, so with every lane
+// reading its quads in the same order the four loads of a wave would fall on
+// a quarter of the LDS banks; lane l reads its quads starting at l mod 4
+// instead, which spreads each load over all of them.  q[j] holds slots
+// 2r and 2r + 1 with r = (j + rot) mod 4.
 struct Bucket {
     uint4 q[kBucketQuads];
+    uint32_t rot;
 };
 
 __device__ __forceinline__ Bucket load_bucket(const uint4* tbl4, uint32_t b) {
     Bucket r;
+    r.rot = __lane_id() & (uint32_t)(kBucketQuads - 1);
 #pragma unroll
-    for (int i = 0; i < kBucketQuads; ++i) r.q[i] = tbl4[kBucketQuads * b + i];
+    for (int i = 0; i < kBucketQuads; ++i)
+        r.q[i] = tbl4[kBucketQuads * b + (((uint32_t)i + r.rot) & (uint32_t)(kBucketQuads - 1))];
     return r;
+}
+
+// Slot order from load order: a left rotation of the 8-bit mask by 2 rot.
+__device__ __forceinline__ uint32_t unrotate_mask(uint32_t m, uint32_t rot) {
+    const uint32_t sh = 2u * rot;
+    return ((m << sh) | (m >> (kBucketSlots - sh))) & ((1u << kBucketSlots) - 1u);
 }
 
 // Slot masks (bit i = slot i of the bucket).  At a window's lookups a bucket
@@ -120,7 +136,7 @@ __device__ __forceinline__ uint32_t match_mask(const Bucket& B, uint32_t x) {
         m |= (B.q[i].x == x ? 1u : 0u) << (2 * i);
         m |= (B.q[i].z == x ? 1u : 0u) << (2 * i + 1);
     }
-    return m;
+    return unrotate_mask(m, B.rot);
 }
 
 __device__ __forceinline__ uint32_t empty_mask(const Bucket& B) {
@@ -130,7 +146,7 @@ __device__ __forceinline__ uint32_t empty_mask(const Bucket& B) {
         m |= (B.q[i].y == kTagEmpty ? 1u : 0u) << (2 * i);
         m |= (B.q[i].w == kTagEmpty ? 1u : 0u) << (2 * i + 1);
     }
-    return m;
+    return unrotate_mask(m, B.rot);
 }
 
 // The free slot an item claims in a bucket with free-slot mask e (nonzero):
@@ -166,15 +182,6 @@ __device__ __forceinline__ uint32_t claim_slot(uint32_t e1, uint32_t e2, uint32_
     return e ? kBucketSlots * b + pick_free(e, x, mult) : kNone;
 }
 
-__device__ __forceinline__ uint32_t tag_at(const Bucket& B, uint32_t i) {
-    uint32_t t = 0;
-#pragma unroll
-    for (int j = 0; j < kBucketQuads; ++j) {
-        t = (i == 2u * j) ? B.q[j].y : t;
-        t = (i == 2u * j + 1) ? B.q[j].w : t;
-    }
-    return t;
-}
 
 
 // ---------------------------------------------------------------------------

@@ -208,7 +208,7 @@ int build_plan(pss_batch* b, const std::vector<uint32_t>& sel, const Tuning& t, 
         while (w > 1 && (size_t)w * cl.lds_stride > ctx->lds_max) w >>= 1;
         if ((size_t)cl.lds_stride > ctx->lds_max) return PSS_ERANGE;
         cl.waves = w;
-        uint64_t per_cu = ctx->lds_per_cu / ((uint64_t)w * cl.lds_stride);
+        uint64_t per_cu = lds_waves(ctx->lds_per_cu, w * cl.lds_stride);
         per_cu = std::max<uint64_t>(1, std::min<uint64_t>(per_cu, 32 / w));
         const uint64_t resident = (uint64_t)std::max(1, ctx->cu_count) * per_cu;
         const uint64_t need = (cl.count + w - 1) / w;

@@ -66,7 +66,21 @@ __device__ unsigned long long g_kstats[32];
 // The item id of the counter in slot s: the key of its table entry.
 struct SlotIds {
     const uint64_t* table;
-    __device__ __forceinline__ uint32_t operator()(uint32_t s) const { return (uint32_t)table[s]; }
+    __device__ __forceinline__ uint32_t operator()(uint32_t s) const { return ((const uint32_t*)table)[2 * s]; }
+};
+
+// LDS pointer types of the level sort's arrays (state in LDS).  The sort's
+// out-of-line parts take these, so that they address LDS with LDS
+// instructions: through a generic pointer a callee would use FLAT ones, and
+// each wait for a FLAT load also waits for the wave's global loads and
+// stores.
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+// SlotIds of a table in LDS (words: the entries as 32-bit words).
+struct LdsIds {
+    const lds_u32* words;
+    __device__ __forceinline__ uint32_t operator()(uint32_t s) const { return words[2 * s]; }
 };
 
 // Count of a slot's entry (the high word), or ~0 when the slot holds no
@@ -136,8 +150,8 @@ __device__ __forceinline__ void reg_bitonic_sort(uint64_t (&v)[P], uint32_t lane
 }
 
 // list[0, len) holds counter indices; reorder them by item id.
-template <int P, typename ID>
-__device__ void sort_level_regs(uint16_t* list, const ID& ids, uint32_t len, uint32_t lane) {
+template <int P>
+__device__ void sort_level_regs(lds_u16* list, const LdsIds ids, uint32_t len, uint32_t lane) {
     uint64_t v[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
@@ -157,8 +171,8 @@ __device__ void sort_level_regs(uint16_t* list, const ID& ids, uint32_t len, uin
     }
 }
 
-template <int P, typename ID>
-__device__ void sort_level_dispatch(uint16_t* list, const ID& ids, uint32_t len, uint32_t per_lane,
+template <int P>
+__device__ void sort_level_dispatch(lds_u16* list, const LdsIds ids, uint32_t len, uint32_t per_lane,
                                     uint32_t lane) {
     if constexpr (P >= 2) {
         if (per_lane == (uint32_t)P) {
@@ -229,23 +243,22 @@ __device__ __forceinline__ void lane_merge(uint64_t (&v)[Q]) {
     }
 }
 
-// Lane l takes positions [l Q, (l+1) Q) of list/tkey (ids in tkey, slots
-// in list, in an order where only entries of one bucket can be out of
-// order), sorts them in registers by (id, slot), and odd-even merges between
+// Lane l takes positions [l Q, (l+1) Q) of list (slots, in an order where
+// only entries of one bucket can be out of order; each slot's id is read
+// from the table), sorts them in registers by (id, slot), and odd-even merges between
 // neighbouring lanes (the lower lane keeping the smaller half) finish the
 // order; the wave stops as soon as every lane's last key is at most its
 // neighbour's first, after at most 64 rounds (odd-even transposition over 64
 // blocks sorts any input).  Out of line: its registers stay apart from the
 // caller's.
 template <int Q>
-__device__ __attribute__((noinline)) void merge_runs(uint16_t* list, const uint32_t* tkey, uint32_t len,
-                                                     uint32_t lane) {
+__device__ __attribute__((noinline)) void merge_runs(lds_u16* list, const LdsIds ids, uint32_t len, uint32_t lane) {
     uint64_t v[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
         const uint32_t g = lane * Q + j;
-        const uint32_t gi = g < len ? g : 0u;
-        const uint64_t key = ((uint64_t)tkey[gi] << 32) | list[gi];
+        const uint32_t s = list[g < len ? g : 0u];
+        const uint64_t key = ((uint64_t)ids(s) << 32) | s;
         v[j] = g < len ? key : ~0ull;
     }
     lane_sort<Q>(v);
@@ -286,52 +299,71 @@ __device__ __attribute__((noinline)) void merge_runs(uint16_t* list, const uint3
 // Bucketed sort of list[0, len) by item id for len > 64, 64 * Q >= len: a
 // counting sort on 8 bits of the id (the top 8 of the bits where the level's
 // ids differ, so bucket order is id order) places every entry in its bucket;
-// then merge_runs orders the entries inside each bucket.  Returns false, with list as it was, when a bucket is larger than
-// kMaxBucket.  OVER: hist lies over list (the list is held in registers
-// from the first read to the scatter).
-template <int Q, bool OVER, typename ID>
-__device__ bool sort_level_buckets(uint16_t* list, const ID& ids, uint32_t* tkey, uint32_t* hist,
-                                   uint32_t len, uint32_t lane) {
-    uint32_t sd[Q], id[Q], pin[Q];
+// then merge_runs orders the entries inside each bucket.  Returns false, with
+// list as it was, when a bucket is larger than kMaxBucket.  hist lies over
+// list (the list is held in registers from the first read to the scatter).
+// A lane keeps each of its Q entries as one word, slot | place in
+// its bucket << 16 (slots and places are below 2^16 with the state in LDS),
+// and their digits four to a word; ids are read from the table when needed,
+// and each step takes the entries eight at a time (a scheduling barrier
+// between groups bounds the loads and atomics in flight).  Out of line, like
+// merge_runs: at large k these registers would otherwise set the kernel's.
+template <int Q>
+__device__ __attribute__((noinline)) bool sort_level_buckets(lds_u16* list, const LdsIds ids, lds_u32* hist,
+                                                             uint32_t len, uint32_t lane) {
+    constexpr int kDigitWords = (Q + 3) / 4;
+    constexpr int kGroup = Q < 8 ? Q : 8;
+    uint32_t sp[Q], dg[kDigitWords];
     uint32_t orv = 0u, andv = 0xFFFFFFFFu;
     SORT_T(0);
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-        const uint32_t g = lane * Q + j;
-        const uint32_t s = list[g < len ? g : 0u];
-        id[j] = ids(s);
-        sd[j] = s;
-        if (g < len) {
-            orv |= id[j];
-            andv &= id[j];
+    for (int j0 = 0; j0 < Q; j0 += kGroup) {
+#pragma unroll
+        for (int j = j0; j < j0 + kGroup; ++j) {
+            const uint32_t g = lane * Q + j;
+            const uint32_t s = list[g < len ? g : 0u];
+            const uint32_t id = ids(s);
+            sp[j] = s;
+            if (g < len) {
+                orv |= id;
+                andv &= id;
+            }
         }
+        __builtin_amdgcn_sched_barrier(0);
     }
     SORT_T(1);
     const uint32_t diff = wave_or_u32(orv) ^ wave_and_u32(andv);
     const uint32_t hb = 31u - (uint32_t)__builtin_clz(diff | 1u);
     const uint32_t shift = hb >= 7u ? hb - 7u : 0u;
+    wave_sync();  // the list is read: the histogram may now overwrite it
     for (uint32_t i = lane; i < 257; i += kWave) hist[i] = 0u;
     wave_sync();
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-        const uint32_t g = lane * Q + j;
-        const uint32_t d = (id[j] >> shift) & 255u;
-        sd[j] |= d << 16;
-        pin[j] = (g < len) ? atomicAdd(&hist[d], 1u) : 0u;
+    for (int w = 0; w < kDigitWords; ++w) dg[w] = 0u;
+#pragma unroll
+    for (int j0 = 0; j0 < Q; j0 += kGroup) {
+#pragma unroll
+        for (int j = j0; j < j0 + kGroup; ++j) {
+            const uint32_t g = lane * Q + j;
+            const uint32_t d = (ids(sp[j]) >> shift) & 255u;
+            dg[j / 4] |= d << (8 * (j % 4));
+            const uint32_t pin =
+                (g < len) ? __hip_atomic_fetch_add(&hist[d], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) : 0u;
+            sp[j] |= pin << 16;
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
     wave_sync();
     SORT_T(2);
     const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
     if (wave_max_u32(max(max(h0, h1), max(h2, h3))) > kMaxBucket) {
-        if constexpr (OVER) {  // put the list back for the fallback
-            wave_sync();
+        wave_sync();  // put the list back for the fallback
 #pragma unroll
-            for (int j = 0; j < Q; ++j) {
-                const uint32_t g = lane * Q + j;
-                if (g < len) list[g] = (uint16_t)(sd[j] & 0xFFFFu);
-            }
-            wave_sync();
+        for (int j = 0; j < Q; ++j) {
+            const uint32_t g = lane * Q + j;
+            if (g < len) list[g] = (uint16_t)(sp[j] & 0xFFFFu);
         }
+        wave_sync();
         return false;
     }
     // exclusive scan of the 256 counts: bucket d starts at hist[d]
@@ -349,40 +381,42 @@ __device__ bool sort_level_buckets(uint16_t* list, const ID& ids, uint32_t* tkey
     hist[4 * lane + 3] = ex + h0 + h1 + h2;
     wave_sync();
 #pragma unroll
-    for (int j = 0; j < Q; ++j) pin[j] += hist[sd[j] >> 16];  // the entry's place in bucket order
+    for (int j0 = 0; j0 < Q; j0 += kGroup) {
+#pragma unroll
+        for (int j = j0; j < j0 + kGroup; ++j)  // the entry's place in bucket order
+            sp[j] = (sp[j] & 0xFFFFu) | ((hist[(dg[j / 4] >> (8 * (j % 4))) & 255u] + (sp[j] >> 16)) << 16);
+        __builtin_amdgcn_sched_barrier(0);
+    }
     wave_sync();  // the histogram is read: list may now overwrite it
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
         const uint32_t g = lane * Q + j;
-        if (g < len) {
-            tkey[pin[j]] = id[j];
-            list[pin[j]] = (uint16_t)(sd[j] & 0xFFFFu);
-        }
+        if (g < len) list[sp[j] >> 16] = (uint16_t)(sp[j] & 0xFFFFu);
     }
     wave_sync();
     SORT_T(3);
-    merge_runs<Q>(list, tkey, len, lane);
+    merge_runs<Q>(list, ids, len, lane);
     SORT_T(4);
     SORT_T(5);
     SORT_FLUSH();
     return true;
 }
 
-template <int P, bool OVER, typename ID>
-__device__ bool sort_level_buckets_dispatch(uint16_t* list, const ID& ids, uint32_t* tkey, uint32_t* hist,
-                                            uint32_t len, uint32_t per_lane, uint32_t lane) {
+template <int P>
+__device__ bool sort_level_buckets_dispatch(lds_u16* list, const LdsIds ids, lds_u32* hist, uint32_t len,
+                                            uint32_t per_lane, uint32_t lane) {
     if constexpr (P >= 2 && P <= 32) {
-        if (per_lane == (uint32_t)P) return sort_level_buckets<P, OVER>(list, ids, tkey, hist, len, lane);
+        if (per_lane == (uint32_t)P) return sort_level_buckets<P>(list, ids, hist, len, lane);
     }
     if constexpr (P > 2)
-        return sort_level_buckets_dispatch<P / 2, OVER>(list, ids, tkey, hist, len, per_lane, lane);
+        return sort_level_buckets_dispatch<P / 2>(list, ids, hist, len, per_lane, lane);
     return false;
 }
 
 // Rank sort of list[0, len) by item id, len <= 64: one entry per lane, its
 // rank is the number of smaller ids.
-template <typename IT, typename ID>
-__device__ void sort_level_rank(IT* list, const ID& ids, uint32_t len, uint32_t lane) {
+template <typename LP, typename ID>
+__device__ void sort_level_rank(LP list, const ID& ids, uint32_t len, uint32_t lane) {
     uint32_t s = 0;
     uint32_t key = 0xFFFFFFFFu;
     if (lane < len) {
@@ -395,7 +429,7 @@ __device__ void sort_level_rank(IT* list, const ID& ids, uint32_t len, uint32_t 
         rank += ki < key ? 1u : 0u;
     }
     wave_sync();
-    if (lane < len) list[rank] = (IT)s;
+    if (lane < len) list[rank] = s;
 }
 
 // Stable least-significant-digit radix sort of list[0, len) by item id (four
@@ -462,15 +496,13 @@ __device__ void sort_level_radix(IT* list, IT* list2, const ID& ids, uint32_t* t
     }
 }
 
-template <int P, typename ID>
-__device__ void sort_level(uint16_t* list, const ID& ids, uint32_t* tkey, uint32_t* hist, uint32_t len,
-                           uint32_t lane) {
-    constexpr bool kOver = P >= (int)kHistOverListMinP;  // the layout's choice for this class
+template <int P>
+__device__ void sort_level(lds_u16* list, const LdsIds ids, lds_u32* hist, uint32_t len, uint32_t lane) {
     if (len <= 64) {
-        sort_level_rank<uint16_t>(list, ids, len, lane);
+        sort_level_rank(list, ids, len, lane);
     } else {
         const uint32_t per_lane = next_pow2((len + 63) / 64);
-        if (!sort_level_buckets_dispatch<P, kOver>(list, ids, tkey, hist, len, per_lane, lane)) {
+        if (!sort_level_buckets_dispatch<P>(list, ids, hist, len, per_lane, lane)) {
             wave_sync();
             sort_level_dispatch<P>(list, ids, len, per_lane, lane);
         }
@@ -494,10 +526,9 @@ __device__ __forceinline__ uint64_t level_lds_body(uint32_t sbo, const ChunkLayo
                                                    uint32_t lane) {
     const uint32_t S = L.slots;
     const uint32_t* words = (const uint32_t*)(smem + sbo + L.off_table);
-    uint16_t* list = (uint16_t*)(smem + sbo + L.off_list);
-    uint32_t* tkey = (uint32_t*)(smem + sbo + L.off_tkey);
-    uint32_t* hist = (uint32_t*)(smem + sbo + L.off_hist);
-    const SlotIds ids{(const uint64_t*)(smem + sbo + L.off_table)};
+    lds_u16* list = (lds_u16*)(smem + sbo + L.off_list);
+    lds_u32* hist = (lds_u32*)(smem + sbo + L.off_hist);
+    const LdsIds ids{(const lds_u32*)(smem + sbo + L.off_table)};
     const uint32_t guess = prev + 1u;
     uint32_t mn = 0xFFFFFFFFu, len = 0;
     for (uint32_t b = 0; b < S; b += 4 * kWave) {
@@ -536,7 +567,7 @@ __device__ __forceinline__ uint64_t level_lds_body(uint32_t sbo, const ChunkLayo
         }
     }
     wave_sync();
-    sort_level<P>(list, ids, tkey, hist, len, lane);
+    sort_level<P>(list, ids, hist, len, lane);
     return ((uint64_t)m << 32) | len;
 }
 
@@ -603,7 +634,7 @@ __device__ __forceinline__ uint64_t build_level_global(unsigned char* sb, unsign
     }
     wave_sync();
     if (len <= 64)
-        sort_level_rank<uint32_t>(list, ids, len, lane);
+        sort_level_rank(list, ids, len, lane);
     else
         sort_level_radix<uint32_t>(list, list2, ids, tkey, tkey2, hist, len, lane);
     wave_sync();

@@ -40,7 +40,7 @@ uint32_t plan_chunks(int cu_count, size_t lds_per_cu, size_t lds_max, uint64_t n
     // enough resident waves to cover every CU a few times over, while keeping
     // blocks long next to k (the reduction tree moves ~C*k entries)
     const ChunkLayout L = chunk_layout(k, lds_max);
-    uint64_t per_cu = lds_per_cu / std::max<uint32_t>(1, L.lds_bytes);
+    uint64_t per_cu = lds_waves(lds_per_cu, L.lds_bytes);
     per_cu = std::min<uint64_t>(std::max<uint64_t>(per_cu, 1), 32);  // 32 waves per CU at most
     // many resident waves (small k): twice the rounds, the tree stays cheap
     uint64_t want = (uint64_t)std::max(cu_count, 1) * per_cu * (per_cu >= 8 ? 2 * kPlanRounds : kPlanRounds);

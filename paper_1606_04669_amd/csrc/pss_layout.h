@@ -18,9 +18,24 @@
 
 namespace pss {
 
-// Items staged per half of the LDS input ring (two halves).
-constexpr uint32_t kRingHalf = 256;
+// Items staged per half of the LDS input ring (two halves): two per lane,
+// which keeps a window (at most 64 items from a position in the first half)
+// inside the ring.
+#ifndef PSS_RING_HALF
+#define PSS_RING_HALF 128
+#endif
+constexpr uint32_t kRingHalf = PSS_RING_HALF;
 constexpr uint32_t kRing = 2 * kRingHalf;
+static_assert(kRingHalf == 128 || kRingHalf == 256, "two or four items per lane");
+// LDS is given to workgroups in units of this many bytes on MI355X (gfx950):
+// a CU of 160 KiB holds floor(163840 / (bytes rounded up to a unit))
+// one-wave workgroups, measured with workgroups of every size used here
+// (the runtime's occupancy query assumes finer units and overestimates).
+constexpr uint32_t kLdsUnit = 1280;
+PSS_HD inline uint32_t lds_waves(uint64_t lds_per_cu, uint32_t bytes) {
+    const uint64_t alloc = (bytes + kLdsUnit - 1) / kLdsUnit * kLdsUnit;
+    return (uint32_t)(lds_per_cu / (alloc ? alloc : kLdsUnit));
+}
 // Largest hash table whose slot positions fit uint16 (LDS-resident state).
 constexpr uint32_t kMaxLdsTableSlots = 65536;
 // Slots per hash bucket (key/tag pairs of 8 bytes).
@@ -44,9 +59,6 @@ constexpr uint32_t kStash = 64;
 constexpr uint64_t kStreamBound = (1ull << 32) - 128;
 // The level sort's histogram: 257 words.
 constexpr uint32_t kHistBytes = 4 * 257;
-// Register classes (sort registers per lane) from which the level sort's
-// histogram lies over the level list (LDS-resident state).
-constexpr uint32_t kHistOverListMinP = 16;
 
 PSS_HD inline uint32_t next_pow2(uint32_t v) {
     uint32_t p = 1;
@@ -105,16 +117,20 @@ struct ChunkLayout {
         // top 128 values: victims and claims of a window), 64-B buckets, then
         // the stash
         L.off_table = o; o = align16(o + 8 * L.slots);
-        // with LDS state and a large register class the level sort keeps the
-        // list in registers and lays its histogram over it
-        const bool hist_over_list = !global_state && sort_lanes_per_k(k) >= kHistOverListMinP;
+        // with LDS state the level sort holds the list in registers from its
+        // first read to its scatter and lays its histogram over it
+        const bool hist_over_list = !global_state;
         const uint32_t list_bytes = idx * k;
         L.off_list = o;                                  // slots of the minimum level, by id
         o = align16(o + (hist_over_list && list_bytes < kHistBytes ? kHistBytes : list_bytes));
-        L.off_tkey = o;  o = align16(o + 4 * k);         // ids while a level is sorted
+        // the radix sort of a level (state in global memory) keeps the ids
+        // beside the slots and ping-pongs both; the LDS sorts read each
+        // slot's id from the table
+        L.off_tkey = o;
         L.off_list2 = o;
         L.off_tkey2 = o;
-        if (global_state) {                              // ping-pong buffers of the radix sort
+        if (global_state) {
+            o = align16(o + 4 * k);
             L.off_list2 = o; o = align16(o + 4 * k);
             L.off_tkey2 = o; o = align16(o + 4 * k);
         }

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "pss_device.h"
 #include "pss_layout.h"
 
@@ -214,22 +216,51 @@ __device__ __forceinline__ uint4 load4(const uint32_t* __restrict__ items, uint6
     return v;
 }
 
-// One half of the ring: 256 items, four per lane.
-static_assert(kRingHalf == 4 * kWave, "one uint4 per lane per ring half");
+// Two consecutive items at idx (even), zero at and beyond stop.
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint2 load2(const uint32_t* __restrict__ items, uint64_t idx, uint64_t n, uint64_t stop,
+                                       int vec_ok) {
+    uint2 v = make_uint2(0u, 0u);
+    if (idx >= stop) return v;
+    if (vec_ok && idx + 1 < n) {
+        const u32x2_t t = PSS_NT_LOAD((const u32x2_t*)(items + idx));
+        v = make_uint2(t[0], t[1]);
+    } else {
+        if (idx < n) v.x = PSS_NT_LOAD(items + idx);
+        if (idx + 1 < n) v.y = PSS_NT_LOAD(items + idx + 1);
+    }
+    return v;
+}
+
+// One half of the ring: kRingHalf items, kRingPerLane per lane (one 8- or
+// 16-byte load).
+constexpr uint32_t kRingPerLane = kRingHalf / kWave;
+static_assert(kRingPerLane == 2 || kRingPerLane == 4, "one uint2 or uint4 per lane per ring half");
 struct Prefetch {
-    uint4 a;
+    typename std::conditional<kRingPerLane == 4, uint4, uint2>::type a;
 };
+
+__device__ __forceinline__ void load_lane(uint4& a, const uint32_t* __restrict__ items, uint64_t tile, uint64_t n,
+                                          uint64_t stop, int vec_ok, uint32_t lane) {
+    a = load4(items, tile + 4 * lane, n, stop, vec_ok);
+}
+
+__device__ __forceinline__ void load_lane(uint2& a, const uint32_t* __restrict__ items, uint64_t tile, uint64_t n,
+                                          uint64_t stop, int vec_ok, uint32_t lane) {
+    a = load2(items, tile + 2 * lane, n, stop, vec_ok);
+}
 
 __device__ __forceinline__ Prefetch fetch_half(const uint32_t* __restrict__ items, uint64_t tile, uint64_t n,
                                                uint64_t stop, int vec_ok, uint32_t lane) {
     Prefetch p;
-    p.a = load4(items, tile + 4 * lane, n, stop, vec_ok);
+    load_lane(p.a, items, tile, n, stop, vec_ok, lane);
     return p;
 }
 
 __device__ __forceinline__ void store_half(uint32_t* ring, uint64_t tile, const Prefetch& p, uint32_t lane) {
     uint32_t base = (uint32_t)tile & (kRing - 1);
-    *(uint4*)(ring + base + 4 * lane) = p.a;
+    *(decltype(p.a)*)(ring + base + kRingPerLane * lane) = p.a;
 }
 
 }  // namespace pss

@@ -398,7 +398,7 @@ int run_launch(pss_server* srv, uint32_t si) {
         while (i < nb && hb[i].cls == cls) kc = std::max(kc, hb[i++].d.k);
         const uint32_t count = i - first;
         const uint32_t stride = align16(ChunkLayout::make(kc, false).lds_bytes);
-        uint64_t per_cu = srv->ctx->lds_per_cu / stride;
+        uint64_t per_cu = lds_waves(srv->ctx->lds_per_cu, stride);
         per_cu = std::max<uint64_t>(1, std::min<uint64_t>(per_cu, 32));
         const uint32_t grid =
             (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)srv->ctx->cu_count * per_cu, count));

@@ -43,14 +43,14 @@ constexpr uint32_t kMaxLdsTableSlots = 65536;
 #define PSS_BUCKET_SLOTS 8
 #endif
 constexpr uint32_t kBucketSlots = PSS_BUCKET_SLOTS;
-// Hash slots per counter x16: 2 per counter up to k = 1024, 1.625 above (a
-// speed / memory trade that never changes results: at k = 2000 the smaller
-// table lets four waves share a CU's LDS).
+// Hash slots per counter x16: 1.875 per counter up to k = 1024, 1.625 above
+// (a speed / memory trade that never changes results: at k = 500 and 2000
+// these are the largest tables with which 16 and 5 waves share a CU's LDS).
 #ifndef PSS_SLOTS_X16
 #define PSS_SLOTS_X16 26
 #endif
 #ifndef PSS_SLOTS_X16_SMALLK
-#define PSS_SLOTS_X16_SMALLK 32
+#define PSS_SLOTS_X16_SMALLK 30
 #endif
 // Overflow slots after the buckets, for items whose two buckets are full.
 constexpr uint32_t kStash = 64;

@@ -132,7 +132,7 @@ def test_benchmark_sizes_fit_their_wave_counts(layouts):
     def waves(b):
         return (160 * 1024) // (-(-b // c["unit"]) * c["unit"])
 
-    assert waves(lds[(500, 0)]) >= 14
+    assert waves(lds[(500, 0)]) >= 16
     assert waves(lds[(2000, 0)]) >= 5
 
 

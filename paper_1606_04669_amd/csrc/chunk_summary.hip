@@ -649,8 +649,8 @@ __device__ __forceinline__ uint64_t build_level_global(unsigned char* sb, unsign
 // P: registers per lane for the in-register level sort (LDS-resident state);
 // G: the state at sb lives in global memory with 32-bit indices (k whose
 // state does not fit LDS), else sb is in LDS.  lds holds the input ring and
-// the per-window arrays; errs is the block's error scratch (one word per
-// slot).  Writes entries [0, size) to o_item/o_cnt/o_err and the header to
+// the per-window arrays; errs is the block's error scratch (one error of
+// L.err_bytes bytes per slot).  Writes entries [0, size) to o_item/o_cnt/o_err and the header to
 // *o_size, *o_min.  Returns kOverflow, with nothing written, when a new
 // item found no free slot under the hash functions hk (the caller runs the
 // block again with other ones); else kDone.
@@ -676,6 +676,20 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
     const SlotIds ids{table};
     uint32_t* ring = (uint32_t*)(lds + L.off_ring);
     const uint4* stash4 = tbl4 + T / 2;
+    // the block's error scratch at the layout's width
+    const uint32_t ew = L.err_bytes;
+    auto err_put = [&](uint32_t s, uint32_t e) {
+        if (ew == 1)
+            ((uint8_t*)errs)[s] = (uint8_t)e;
+        else if (ew == 2)
+            ((uint16_t*)errs)[s] = (uint16_t)e;
+        else
+            errs[s] = e;
+    };
+    auto err_get = [&](uint32_t s) -> uint32_t {
+        return ew == 1 ? (uint32_t)((const uint8_t*)errs)[s]
+                       : ew == 2 ? (uint32_t)((const uint16_t*)errs)[s] : errs[s];
+    };
 
     const uint32_t ekey = uniform(empty_key_e1(NB, hk));  // key of empty slots in buckets 0 and 1
     if (ekey == 0u) return kOverflow;  // unusable hash functions: the caller tries others
@@ -744,7 +758,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
                     const uint64_t emp = empty_entry(ekey, dst);
                     if (atomicCAS((unsigned long long*)&table[dst], (unsigned long long)emp, (unsigned long long)e) ==
                         emp) {
-                        errs[dst] = errs[T + lane];
+                        err_put(dst, err_get(T + lane));
                         table[T + lane] = 0ull;
                         moved = true;
                     }
@@ -1007,7 +1021,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
         if (in && hit) atomicAdd(&words[2 * slot + 1], 1u);
         if (newf) {
             if (in) {
-                errs[hp] = full ? m : 0u;
+                err_put(hp, full ? m : 0u);
                 table[hp] = make_entry(x, full ? m + 1u : 1u);
             } else {
                 table[hp] = empty_entry(ekey, hp);
@@ -1068,7 +1082,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
             const uint32_t o = outn + mbcnt(bm);
             o_item[o] = (uint32_t)e;
             o_cnt[o] = c;
-            o_err[o] = errs[s];
+            o_err[o] = err_get(s);
             mn = min(mn, c);
         }
         outn = uniform(outn + popc64(bm));
@@ -1229,10 +1243,13 @@ ChunkLayout chunk_layout(uint32_t k, size_t lds_max) {
     return ChunkLayout::make(k, true);
 }
 
-hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L,
+hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L0,
                                 const BlockSummaries& out, unsigned char* gstate, uint32_t* errs,
                                 hipStream_t stream) {
     const int vec_ok = ((uintptr_t)d_items & 15u) == 0;
+    if (chunks == 0) return hipErrorInvalidValue;
+    // blocks hold at most ceil(n / chunks) items
+    const ChunkLayout L = L0.with_error_width((n + chunks - 1) / chunks);
     if (!errs) return hipErrorInvalidValue;
     if (L.global_state) {
         if (!gstate) return hipErrorInvalidValue;

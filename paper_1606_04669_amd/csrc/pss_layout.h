@@ -91,9 +91,10 @@ struct ChunkLayout {
     // LDS offsets (bytes from the LDS base; the state comes first when it is in LDS)
     uint32_t off_ring, off_hist;
     uint32_t lds_bytes;
-    // per-block error scratch in device memory: one uint32 per slot, blocks
-    // err_stride words apart (a multiple of 32: each block starts a cache line)
-    uint32_t err_stride;
+    // per-block error scratch in device memory: one error per slot, blocks
+    // err_stride words apart (a multiple of 32: each block starts a cache
+    // line); err_bytes per error (4, or 2 / 1 by with_error_width)
+    uint32_t err_stride, err_bytes;
 
     // Default hash slots per counter (x16).
     PSS_HD static uint32_t default_slots_x16(uint32_t k) { return k <= 1024 ? PSS_SLOTS_X16_SMALLK : PSS_SLOTS_X16; }
@@ -145,7 +146,20 @@ struct ChunkLayout {
         }
         L.lds_bytes = l;
         L.err_stride = (L.slots + 31u) & ~31u;
+        L.err_bytes = 4;
         return L;
+    }
+
+    // This layout with the narrowest errors that hold every error of blocks
+    // of at most max_block items: an error is a count of the minimum level at
+    // an install, at most max_block / k.  Narrow errors shrink a block's
+    // scratch footprint, so fewer of its lines are written back to memory
+    // while the input stream passes through the L2.
+    PSS_HD ChunkLayout with_error_width(uint64_t max_block) const {
+        ChunkLayout R = *this;
+        const uint64_t top = max_block / k;
+        R.err_bytes = top < 255u ? 1u : top < 65535u ? 2u : 4u;
+        return R;
     }
 
     PSS_HD bool fits_lds_indices() const { return slots <= kMaxLdsTableSlots && k <= 65535u; }

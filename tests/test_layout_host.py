@@ -41,6 +41,14 @@ int main() {
             if (g || k <= 8192) emit(k, g);
     }
     printf("]\n");
+    // error widths at the boundaries: blocks of 255 k - 1, 255 k, 65535 k - 1, 65535 k items
+    for (unsigned k : {2u, 500u, 2000u, 50000u}) {
+        ChunkLayout L = ChunkLayout::make(k, k > 4096);
+        printf("%u %u %u %u %u ", L.err_bytes, L.with_error_width(255ull * k - 1).err_bytes,
+               L.with_error_width(255ull * k).err_bytes, L.with_error_width(65535ull * k - 1).err_bytes,
+               L.with_error_width(65535ull * k).err_bytes);
+    }
+    printf("\n");
     printf("%u %u %u %llu %u %u\n", kBucketSlots, kStash, kHistBytes, (unsigned long long)kStreamBound, kRing, kLdsUnit);
     for (unsigned b : {1u, 1280u, 1281u, 11520u, 11600u, 32000u, 32608u})
         printf("%u ", lds_waves(163840, b));
@@ -63,9 +71,10 @@ def layouts(tmp_path_factory):
                         text=True)
     assert cc.returncode == 0, cc.stderr
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines()
-    consts = [int(v) for v in out[1].split()]
-    c = dict(zip(["bucket", "stash", "hist", "bound", "ring", "unit"], consts))
-    c["waves"] = [int(v) for v in out[2].split()]
+    c = {"ewidth": [int(v) for v in out[1].split()]}
+    consts = [int(v) for v in out[2].split()]
+    c.update(zip(["bucket", "stash", "hist", "bound", "ring", "unit"], consts))
+    c["waves"] = [int(v) for v in out[3].split()]
     return json.loads(out[0]), c
 
 
@@ -140,3 +149,10 @@ def test_stream_bound_leaves_room_for_the_window_tags(layouts):
     _, c = layouts
     # two tag ranges of 64 values (victim ranks, claiming lanes) above every count
     assert c["bound"] == (1 << 32) - 128
+
+
+def test_error_width_holds_every_error(layouts):
+    # an error is at most (block length) / k: bytes below 255 k items per
+    # block, 16 bits below 65535 k, else 32 bits; make() keeps 32 bits
+    _, c = layouts
+    assert c["ewidth"] == [4, 1, 2, 2, 4] * 4

@@ -43,6 +43,7 @@ struct ClassLaunch {
     uint32_t lds_stride = 0;
     uint32_t waves = 1;
     uint32_t grid = 0;
+    uint64_t items = 0;  // items of the class's blocks
 };
 
 struct Level {
@@ -196,6 +197,7 @@ int build_plan(pss_batch* b, const std::vector<uint32_t>& sel, const Tuning& t, 
         while (i < b->nblocks && hb[i].cls == cls) {
             kc = std::max(kc, hb[i].d.k);
             slots = std::max(slots, hb[i].d.slots_x16);
+            cl.items += hb[i].d.end - hb[i].d.begin;
             ++i;
         }
         cl.count = i - cl.first;
@@ -297,7 +299,20 @@ int enqueue(pss_batch* b, hipStream_t st) {
     int rc = check(launch_zero_words(b->d_queues, kMaxClasses, st));
     if (rc != PSS_OK) return rc;
     if (hipEventRecord(b->fork, st) != hipSuccess) return PSS_EDEVICE;
-    for (size_t i = 0; i < b->classes.size(); ++i) {
+    // the class with the most work first: the classes share the device's few
+    // hardware queues, and the last one to start finishes the batch.  Work is
+    // estimated as items x (1 + log2 of the sort class): larger k costs more
+    // per item.
+    uint32_t order[kMaxClasses];
+    const size_t nc = b->classes.size();
+    auto work = [&](size_t i) {
+        const ClassLaunch& c = b->classes[i];
+        return (double)c.items * (1.0 + (double)log2_pow2(c.sort_lanes));
+    };
+    for (size_t i = 0; i < nc; ++i) order[i] = (uint32_t)i;
+    std::sort(order, order + nc, [&](uint32_t a, uint32_t c) { return work(a) > work(c); });
+    for (size_t oi = 0; oi < nc; ++oi) {
+        const size_t i = order[oi];
         const ClassLaunch& cl = b->classes[i];
         hipStream_t ss = b->side[i];
         if (hipStreamWaitEvent(ss, b->fork, 0) != hipSuccess) return PSS_EDEVICE;

@@ -1163,7 +1163,7 @@ __global__ __launch_bounds__(64 * W) void batch_blocks_kernel(const BatchBlock* 
         b = __builtin_amdgcn_readlane(b, 0);
         if (b >= nblocks) break;
         const BatchBlock bb = blocks[b];
-        const ChunkLayout L = ChunkLayout::make(bb.k, false, bb.slots_x16);
+        const ChunkLayout L = ChunkLayout::make(bb.k, false, bb.slots_x16).with_error_width(bb.end - bb.begin);
         const int vec_ok = ((uintptr_t)bb.items & 15u) == 0;
         summarize_block_any<P, false>(bb.items, bb.n, bb.begin, bb.end, L, vec_ok, lds, lds, errs + bb.eoff,
                                   o_item + bb.out, o_cnt + bb.out, o_err + bb.out, o_size + b, o_min + b);

@@ -381,11 +381,11 @@ def roofline_of(streams, ks, n_items, phase, nlaunch, peak, measured):
     return dom, inst, per_case, blend
 
 
-def highk_leg(B, ctx, seed: int, steps: int, warmup: int):
+def highk_leg(B, ctx, seed: int, steps: int, warmup: int, tuned: bool):
     """The high-k workload: n = 2^31 (Zipf 1.1 over 2^32 hashed ids and the
     adversarial round-robin stream with a planted 5% item), k in {10^4,
-    5 x 10^4}, the planner's chunk count; block state, COMBINE arrays and
-    the report in device memory."""
+    5 x 10^4}, the chunk count from the tuner (or the planner); block state,
+    COMBINE arrays and the report in device memory."""
     import numpy as np
     import torch
     streams, ks = workload_cases("plain-highk", 31, seed)
@@ -398,8 +398,12 @@ def highk_leg(B, ctx, seed: int, steps: int, warmup: int):
         dev.append(torch.from_numpy(a.view(np.int32)).to("cuda"))
         del a
         log("highk: generated %s in %.1fs" % (st.name, time.perf_counter() - t))
-    chunks_of = {(st.name, k): ctx.plan_chunks(n, k) for st in streams for k in ks}
     stream = torch.cuda.current_stream()
+    chunks_of = {}
+    for st, d in zip(streams, dev):
+        for k in ks:
+            chunks_of[(st.name, k)] = ctx.tune_chunks(d, k, stream=stream)[0] if tuned else ctx.plan_chunks(n, k)
+    log("highk chunk counts: %s" % {"%s/k=%d" % key: v for key, v in chunks_of.items()})
     elapsed, wall, phase, nlaunch = run_cases(B, ctx, streams, dev, ks, chunks_of, steps, warmup, stream)
     items = n * len(streams) * len(ks) * steps
     cases = []
@@ -417,8 +421,8 @@ def highk_leg(B, ctx, seed: int, steps: int, warmup: int):
     del dev
     torch.cuda.empty_cache()
     return {
-        "workload": "plain-highk: n=2^31 per stream, streams=%s, k=%s, chunks from the planner"
-                    % ([s.name for s in streams], ks),
+        "workload": "plain-highk: n=2^31 per stream, streams=%s, k=%s, chunks from the %s"
+                    % ([s.name for s in streams], ks, "tuner (pss_tune_chunks)" if tuned else "planner"),
         "g_items_per_s": round(items / elapsed / 1e9, 3),
         "cases": cases,
         "roofline": {"bound": "hbm", "kernel": "chunk_summary_kernel (state in device memory)",
@@ -682,7 +686,7 @@ def main():
     if args.workload == "plain-large" and not args.no_sweep:
         result["sweep"] = sweep_leg(B, ctx, args.seed, n_log2, [500, 2000, 8000], 3)
     if args.workload == "plain-large" and not args.no_highk:
-        result["highk"] = highk_leg(B, ctx, args.seed, 2, 1)
+        result["highk"] = highk_leg(B, ctx, args.seed, 2, 1, args.chunks == "tuned")
     if not args.no_batched:
         result["batched"] = batched_leg(B, ctx, args.seed, args.batched_replays, args.batched_streams)
     if not args.no_served:

@@ -111,8 +111,9 @@ uint32_t pss_plan_chunks(const pss_ctx* ctx, uint64_t n, uint32_t k);
 /* Autotuner for the chunk count C (Algorithm 1's number of blocks), the one
  * parameter that changes results: times the block summaries and the
  * reduction tree over d_items[0, n) with k counters for C in {P/4, P/2, P,
- * 2P}, P = pss_plan_chunks(n, k) (one warm-up and the best of two timed runs
- * each), and returns the fastest in *best_chunks (its time in *best_ms, may
+ * 2P}, P = pss_plan_chunks(n, k) (with block state in device memory, none
+ * beyond the planner's 16-GiB state budget; one warm-up and the best of two
+ * timed runs each), and returns the fastest in *best_chunks (its time in *best_ms, may
  * be NULL).  Pass the result as `chunks` to pss_update / pss_run and record
  * it: a CPU replay with the same C reproduces the results.  Every call
  * times afresh (the best C depends on the data).  Blocks until done; uses the

@@ -433,13 +433,33 @@ __device__ void sort_level_rank(LP list, const ID& ids, uint32_t len, uint32_t l
 }
 
 // Stable least-significant-digit radix sort of list[0, len) by item id (four
-// 8-bit passes), for levels of any size.  Within each group of 64 entries the
-// lanes holding the same digit are found with eight ballots, so equal digits
-// keep their order.  list2, tkey and tkey2 hold len entries each.
+// 8-bit passes), for levels of any size (the state in device memory).
+// Within each group of 64 entries the lanes holding the same digit are found
+// with eight ballots, so equal digits keep their order.  list2, tkey and
+// tkey2 hold len entries each.  Every loop takes kRadixGroups groups of 64
+// entries at a time and issues all their loads before using any: each step
+// otherwise waits a full device-memory round trip.
+constexpr uint32_t kRadixGroups = 8;
+
 template <typename IT, typename ID>
 __device__ void sort_level_radix(IT* list, IT* list2, const ID& ids, uint32_t* tkey, uint32_t* tkey2,
                                  uint32_t* hist, uint32_t len, uint32_t lane) {
-    for (uint32_t g = lane; g < len; g += kWave) tkey[g] = ids(list[g]);
+    constexpr uint32_t U = kRadixGroups;
+    for (uint32_t base = 0; base < len; base += U * kWave) {
+        uint32_t sl[U], key[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t g = base + u * kWave + lane;
+            sl[u] = (uint32_t)list[g < len ? g : 0u];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) key[u] = ids(sl[u]);
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t g = base + u * kWave + lane;
+            if (g < len) tkey[g] = key[u];
+        }
+    }
     wave_sync();
     IT* src = list;
     IT* dst = list2;
@@ -449,7 +469,19 @@ __device__ void sort_level_radix(IT* list, IT* list2, const ID& ids, uint32_t* t
         const uint32_t sh = 8u * pass;
         for (uint32_t i = lane; i < 256; i += kWave) hist[i] = 0u;
         wave_sync();
-        for (uint32_t g = lane; g < len; g += kWave) atomicAdd(&hist[(ks[g] >> sh) & 255u], 1u);
+        for (uint32_t base = 0; base < len; base += U * kWave) {
+            uint32_t key[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t g = base + u * kWave + lane;
+                key[u] = ks[g < len ? g : 0u];
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t g = base + u * kWave + lane;
+                if (g < len) atomicAdd(&hist[(key[u] >> sh) & 255u], 1u);
+            }
+        }
         wave_sync();
         const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
         const uint32_t sum = h0 + h1 + h2 + h3;
@@ -465,27 +497,38 @@ __device__ void sort_level_radix(IT* list, IT* list2, const ID& ids, uint32_t* t
         hist[4 * lane + 2] = ex + h0 + h1;
         hist[4 * lane + 3] = ex + h0 + h1 + h2;
         wave_sync();
-        for (uint32_t base = 0; base < len; base += kWave) {
-            const uint32_t g = base + lane;
-            const bool v = g < len;
-            const uint32_t key = ks[v ? g : 0u];
-            const IT sv = src[v ? g : 0u];
-            const uint32_t d = (key >> sh) & 255u;
-            uint64_t same = ballot(v);
+        for (uint32_t base = 0; base < len; base += U * kWave) {
+            uint32_t key[U];
+            IT sv[U];
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const uint64_t bb = ballot(v && ((d >> b) & 1u));
-                same &= ((d >> b) & 1u) ? bb : ~bb;
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t g = base + u * kWave + lane;
+                const bool v = g < len;
+                key[u] = ks[v ? g : 0u];
+                sv[u] = src[v ? g : 0u];
             }
-            const uint32_t rank = mbcnt(same);
-            const uint32_t off = hist[d];
-            wave_sync();
-            if (v && rank == 0) hist[d] = off + popc64(same);
-            if (v) {
-                dst[off + rank] = sv;
-                kd[off + rank] = key;
+            // the groups in order: each one's places follow the earlier ones'
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t g = base + u * kWave + lane;
+                const bool v = g < len;
+                const uint32_t d = (key[u] >> sh) & 255u;
+                uint64_t same = ballot(v);
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const uint64_t bb = ballot(v && ((d >> b) & 1u));
+                    same &= ((d >> b) & 1u) ? bb : ~bb;
+                }
+                const uint32_t rank = mbcnt(same);
+                const uint32_t off = hist[d];
+                wave_sync();
+                if (v && rank == 0) hist[d] = off + popc64(same);
+                if (v) {
+                    dst[off + rank] = sv[u];
+                    kd[off + rank] = key[u];
+                }
+                wave_sync();
             }
-            wave_sync();
         }
         IT* t1 = src;
         src = dst;
@@ -536,7 +579,8 @@ __device__ __forceinline__ uint64_t level_lds_body(uint32_t sbo, const ChunkLayo
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t s = b + j * kWave + lane;
-            cv[j] = s < S ? slot_count(words, s) : 0xFFFFFFFFu;
+            const uint32_t c = slot_count(words, s < S ? s : 0u);  // clamped: no branch around the load
+            cv[j] = s < S ? c : 0xFFFFFFFFu;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -555,7 +599,8 @@ __device__ __forceinline__ uint64_t level_lds_body(uint32_t sbo, const ChunkLayo
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const uint32_t s = b + j * kWave + lane;
-                cv[j] = s < S ? slot_count(words, s) : 0xFFFFFFFFu;
+                const uint32_t c = slot_count(words, s < S ? s : 0u);  // clamped: no branch around the load
+            cv[j] = s < S ? c : 0xFFFFFFFFu;
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -597,15 +642,18 @@ __device__ __forceinline__ uint64_t build_level_global(unsigned char* sb, unsign
     const SlotIds ids{(const uint64_t*)(sb + L.off_table)};
     const uint32_t guess = prev + 1u;
     uint32_t mn = 0xFFFFFFFFu, len = 0;
-    for (uint32_t b = 0; b < S; b += 4 * kWave) {
-        uint32_t cv[4];
+    // 16 slots per lane per step, their loads in flight together
+    constexpr int J = 16;
+    for (uint32_t b = 0; b < S; b += J * kWave) {
+        uint32_t cv[J];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < J; ++j) {
             const uint32_t s = b + j * kWave + lane;
-            cv[j] = s < S ? slot_count(words, s) : 0xFFFFFFFFu;
+            const uint32_t c = slot_count(words, s < S ? s : 0u);  // clamped: no branch around the load
+            cv[j] = s < S ? c : 0xFFFFFFFFu;
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < J; ++j) {
             mn = min(mn, cv[j]);
             const bool take = cv[j] == guess;
             const uint64_t bm = ballot(take);
@@ -616,15 +664,16 @@ __device__ __forceinline__ uint64_t build_level_global(unsigned char* sb, unsign
     const uint32_t m = uniform(wave_min_u32(mn));
     if (m != guess) {
         len = 0;
-        for (uint32_t b = 0; b < S; b += 4 * kWave) {
-            uint32_t cv[4];
+        for (uint32_t b = 0; b < S; b += J * kWave) {
+            uint32_t cv[J];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < J; ++j) {
                 const uint32_t s = b + j * kWave + lane;
-                cv[j] = s < S ? slot_count(words, s) : 0xFFFFFFFFu;
+                const uint32_t c = slot_count(words, s < S ? s : 0u);  // clamped: no branch around the load
+            cv[j] = s < S ? c : 0xFFFFFFFFu;
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < J; ++j) {
                 const bool take = cv[j] == m;
                 const uint64_t bm = ballot(take);
                 if (take) list[len + mbcnt(bm)] = b + j * kWave + lane;

@@ -346,8 +346,10 @@ int pss_tune_chunks(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t 
     const KPlan kp = kplan(ctx, k);
     const uint32_t base = pss_plan_chunks(ctx, n, k);
     std::vector<uint32_t> cand;
+    // with the block state in device memory, no candidate beyond the planner's state budget
+    const uint64_t cap = kp.L.global_state ? kStateBudget / (kp.L.state_bytes + 4ull * kp.L.err_stride) : kMaxChunks;
     for (uint64_t c : {(uint64_t)base / 4, (uint64_t)base / 2, (uint64_t)base, (uint64_t)2 * base}) {
-        c = std::max<uint64_t>(1, std::min<uint64_t>({c, (uint64_t)kMaxChunks, n}));
+        c = std::max<uint64_t>(1, std::min<uint64_t>({c, (uint64_t)kMaxChunks, cap, n}));
         if (std::find(cand.begin(), cand.end(), (uint32_t)c) == cand.end()) cand.push_back((uint32_t)c);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -1286,10 +1286,23 @@ static hipError_t launch_p(const uint32_t* d_items, uint64_t n, uint32_t chunks,
     return hipGetLastError();
 }
 
+// Waves per CU for blocks whose state lives in device memory.  Their table
+// accesses miss the L2, and with every CU full of waves (16 by registers)
+// the blocks' states (284 KiB each at k = 10^4) far exceed the last-level
+// cache, so every access went to HBM; with four waves per CU the k = 10^4
+// states (~290 MiB) mostly stay in it.  Measured on the 2^31-item high-k
+// streams: 4 waves per CU are 25-34% faster at k = 10^4 than 16 and equal at
+// k = 5 x 10^4; 2 and 8 are slower.  The layout asks for a quarter of the
+// CU's LDS so that no more waves fit.
+constexpr uint32_t kGlobalStateWavesPerCu = 4;
+
 ChunkLayout chunk_layout(uint32_t k, size_t lds_max) {
     const ChunkLayout L = ChunkLayout::make(k, false);
     if (L.fits_lds_indices() && L.lds_bytes <= lds_max && sort_lanes_per_k(k) <= 64) return L;
-    return ChunkLayout::make(k, true);
+    ChunkLayout G = ChunkLayout::make(k, true);
+    const uint32_t quarter = (uint32_t)(lds_max / kGlobalStateWavesPerCu) / kLdsUnit * kLdsUnit;
+    if (quarter > G.lds_bytes) G.lds_bytes = quarter;
+    return G;
 }
 
 hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L0,

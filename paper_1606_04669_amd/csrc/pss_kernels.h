@@ -37,7 +37,8 @@ struct DevEntry {
 };
 
 // Layout of one block summary for k counters: state in LDS when it fits in
-// lds_max bytes (with 16-bit indices), else in a global slab per block.
+// lds_max bytes (with 16-bit indices), else in a global slab per block, with
+// an LDS request that leaves room for four such waves per CU.
 ChunkLayout chunk_layout(uint32_t k, size_t lds_max);
 // gstate: chunks * L.state_bytes bytes of device memory when L.global_state;
 // errs: chunks * L.err_stride words of device memory (error scratch; the

@@ -21,6 +21,9 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
     "-Wno-unused-value",
+    # a local that shadows another has broken a kernel once: make it an error
+    "-Wshadow",
+    "-Werror=shadow",
 ]
 
 

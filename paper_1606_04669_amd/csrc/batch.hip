@@ -152,7 +152,7 @@ int build_plan(pss_batch* b, const std::vector<uint32_t>& sel, const Tuning& t, 
             h.d.out = 0;
             h.d.eoff = 0;
             h.d.k = k;
-            h.d.slots_x16 = t.slots_x16 ? t.slots_x16 : ChunkLayout::default_slots_x16(k);
+            h.d.slots_x16 = t.slots_x16 ? t.slots_x16 : ChunkLayout::default_slots_x16(k, hash_choices(k, false));
             h.cls = class_index(class_lanes(k));
             h.stream = s;
             h.c = c;

@@ -740,9 +740,24 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
                        : ew == 2 ? (uint32_t)((const uint16_t*)errs)[s] : errs[s];
     };
 
-    const uint32_t ekey = uniform(empty_key_e1(NB, hk));  // key of empty slots in buckets 0 and 1
+    // buckets per item: three in the LDS classes above k = 1024 (the layout's
+    // table is sized for them), two elsewhere
+    constexpr int NCH = (!G && P >= 32) ? 3 : 2;
+    if (L.choices != (uint32_t)NCH) {  // a layout built for another table shape
+        if (lane == 0) {
+            *o_size = kBlockFailed;
+            *o_min = 0;
+        }
+        return kDone;
+    }
+    // the item's third bucket, or none (its mask stays 0)
+    auto bucket3 = [&](uint32_t y, uint32_t c1, uint32_t c2) -> uint32_t {
+        if constexpr (NCH == 3) return third_bucket(y, NB, c1, c2, hk);
+        return 0u;
+    };
+    const uint32_t ekey = uniform(empty_key_e1<NCH>(NB, hk));  // key of empty slots in the first NCH buckets
     if (ekey == 0u) return kOverflow;  // unusable hash functions: the caller tries others
-    for (uint32_t i = lane; i < S; i += kWave) table[i] = empty_entry(ekey, i);
+    for (uint32_t i = lane; i < S; i += kWave) table[i] = empty_entry<NCH>(ekey, i);
 
     // Wave-uniform state.  Every update goes through uniform() so the compiler
     // keeps it in scalar registers and every loop that contains wave-wide
@@ -797,14 +812,23 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
             const bool cand = slive && (!full || c != m);
             if (ballot(cand)) {
                 const uint32_t s1 = home_bucket(skey, NB, hk), s2 = alt_bucket(skey, NB, s1, hk);
+                const uint32_t s3 = bucket3(skey, s1, s2);
                 const Bucket B1 = load_bucket(tbl4, s1), B2 = load_bucket(tbl4, s2);
                 const uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2);
+                uint32_t e3 = 0u;
+                if constexpr (NCH == 3) e3 = empty_mask(load_bucket(tbl4, s3));
                 bool moved = false;
-                if (cand && (e1 | e2)) {
-                    const uint32_t dst = __builtin_popcount(e1) >= __builtin_popcount(e2)
-                                             ? kBucketSlots * s1 + (uint32_t)__builtin_ctz(e1)
-                                             : kBucketSlots * s2 + (uint32_t)__builtin_ctz(e2);
-                    const uint64_t emp = empty_entry(ekey, dst);
+                if (cand && (e1 | e2 | e3)) {
+                    // the emptiest bucket (the earliest on ties), its first free slot
+                    const uint32_t n1 = __builtin_popcount(e1), n2 = __builtin_popcount(e2);
+                    const bool first = n1 >= n2;
+                    uint32_t fm = first ? e1 : e2, fb = first ? s1 : s2;  // free-slot mask, bucket
+                    if (__builtin_popcount(e3) > (first ? n1 : n2)) {
+                        fm = e3;
+                        fb = s3;
+                    }
+                    const uint32_t dst = kBucketSlots * fb + (uint32_t)__builtin_ctz(fm);
+                    const uint64_t emp = empty_entry<NCH>(ekey, dst);
                     if (atomicCAS((unsigned long long*)&table[dst], (unsigned long long)emp, (unsigned long long)e) ==
                         emp) {
                         err_put(dst, err_get(T + lane));
@@ -838,18 +862,25 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
         const bool early = last_slow && full && list_ptr < list_len;
         if (early) fetch_victims();
 
-        // 1. look up against the state at window start: the item's two buckets
-        //    (eight 16-byte loads, branch-free), then the stash while it is used
+        // 1. look up against the state at window start: the item's buckets
+        //    (four 16-byte loads each, branch-free), then the stash while it
+        //    is used
         bool hit = false, miss = false, bad = false, nofree = false;
         uint32_t slot = 0, hp = kNone;
         const uint32_t b1 = home_bucket(x, NB, hk);
         const uint32_t b2 = alt_bucket(x, NB, b1, hk);
+        const uint32_t b3 = bucket3(x, b1, b2);
         Bucket B1 = load_bucket(tbl4, b1), B2 = load_bucket(tbl4, b2);
+        Bucket B3;
+        if constexpr (NCH == 3) B3 = load_bucket(tbl4, b3);
         {
             const uint32_t h1 = match_mask(B1, x), h2 = match_mask(B2, x);
-            slot = h1 ? kBucketSlots * b1 + (uint32_t)__builtin_ctz(h1)
-                      : kBucketSlots * b2 + ((uint32_t)__builtin_ctz(h2 | (1u << kBucketSlots)) & (kBucketSlots - 1));
-            hit = valid && (h1 | h2) != 0u;
+            uint32_t h3 = 0u;
+            if constexpr (NCH == 3) h3 = match_mask(B3, x);
+            const uint32_t hb = h1 ? b1 : h2 ? b2 : b3;
+            const uint32_t hm = h1 ? h1 : h2 ? h2 : h3;
+            slot = kBucketSlots * hb + ((uint32_t)__builtin_ctz(hm | (1u << kBucketSlots)) & (kBucketSlots - 1));
+            hit = valid && (h1 | h2 | h3) != 0u;
         }
         KSTAT_ADD(16, stash_live ? 1 : 0);
         // the stash's live keys, one by one from the lanes holding them
@@ -879,7 +910,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
         // 2. group unmonitored items by value: one claimed slot per value,
         //    tagged with the lowest lane holding it
         const unsigned long long tp = KSTAT_NOW();
-        //    Each lane claims a free slot of its emptier bucket (else of the
+        //    Each lane claims a free slot of its emptiest bucket (else of the
         //    stash) with a compare-and-swap, working from the buckets as the
         //    lookup read them: no claim exists at window start, and a lost
         //    swap returns the slot's new entry -- a claim of the same value
@@ -887,22 +918,23 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
         //    (the slot leaves the lane's view).  Lanes holding equal values
         //    see the same buckets and the same outcomes, so they pick the same
         //    slots.  Every lost swap removes a slot from the view, so the loop
-        //    ends within 16 + 64 rounds.  The claimed slot becomes the new
+        //    ends within 8 NCH + 64 rounds.  The claimed slot becomes the new
         //    counter if the item is installed.
 #ifdef PSS_KERNEL_STATS
         uint32_t steps_seen = 0;
 #endif
         if (miss) {
             const uint64_t mine = make_entry(x, kTagPend + lane);
-            uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2);
+            uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2), e3 = 0u;
+            if constexpr (NCH == 3) e3 = empty_mask(B3);
             uint32_t steps = 0;
             for (;;) {
                 uint32_t h = kNone;
                 bool join = false;
-                if (e1 | e2) {
-                    h = claim_slot(e1, e2, b1, b2, x, hk.pick);
+                if (e1 | e2 | e3) {
+                    h = claim_slot(e1, e2, e3, b1, b2, b3, x, hk.pick);
                 } else {
-                    // both buckets full: the value's claim, or a free slot, in the stash
+                    // all its buckets full: the value's claim, or a free slot, in the stash
                     uint32_t fe = kNone;
                     for (uint32_t i = 0; i < kStash / 2; ++i) {
                         const uint4 e = stash4[i];
@@ -925,7 +957,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
                     break;
                 }
                 if (!join) {
-                    const uint64_t emp = empty_entry(ekey, h);
+                    const uint64_t emp = empty_entry<NCH>(ekey, h);
                     const uint64_t old =
                         atomicCAS((unsigned long long*)&table[h], (unsigned long long)emp, (unsigned long long)mine);
                     if (old == emp) {
@@ -935,7 +967,13 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
                     join = (uint32_t)old == x && (uint32_t)(old >> 32) >= kTagPend;
                     if (!join && h < T) {  // taken by another value
                         const uint32_t bit = 1u << (h % kBucketSlots);
-                        if (h / kBucketSlots == b1) e1 &= ~bit; else e2 &= ~bit;
+                        const uint32_t hb = h / kBucketSlots;
+                        if (hb == b1)
+                            e1 &= ~bit;
+                        else if (hb == b2)
+                            e2 &= ~bit;
+                        else
+                            e3 &= ~bit;
                     }
                 }
                 if (join) {
@@ -943,7 +981,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
                     hp = h;
                     break;
                 }
-                if (++steps > 2 * kBucketSlots + kStash) {
+                if (++steps > (uint32_t)NCH * kBucketSlots + kStash) {
                     bad = true;
                     break;
                 }
@@ -1061,7 +1099,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
         if (full) {
             if (vv) {
                 if (vr < rp)
-                    table[vs] = empty_entry(ekey, vs);
+                    table[vs] = empty_entry<NCH>(ekey, vs);
                 else
                     words[2 * vs + 1] = m;
             }
@@ -1073,7 +1111,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
                 err_put(hp, full ? m : 0u);
                 table[hp] = make_entry(x, full ? m + 1u : 1u);
             } else {
-                table[hp] = empty_entry(ekey, hp);
+                table[hp] = empty_entry<NCH>(ekey, hp);
             }
         }
         const bool repeat = in && miss && !newf;

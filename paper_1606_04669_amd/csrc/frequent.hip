@@ -54,9 +54,9 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
     const uint4* stash4 = tbl4 + T / 2;
     uint32_t* ring = (uint32_t*)(lds + L.off_ring);
 
-    const uint32_t ekey = uniform(empty_key_e1(NB, hk));  // key of empty slots in buckets 0 and 1
+    const uint32_t ekey = uniform(empty_key_e1<2>(NB, hk));  // key of empty slots in buckets 0 and 1
     if (ekey == 0u) return kFqOverflow;  // unusable hash functions: the caller tries others
-    for (uint32_t i = lane; i < S; i += kWave) table[i] = empty_entry(ekey, i);
+    for (uint32_t i = lane; i < S; i += kWave) table[i] = empty_entry<2>(ekey, i);
 
     // wave-uniform state (readfirstlane-anchored, see the Space Saving kernel)
     uint32_t size = 0, dec = 0, failed = 0, stash_live = 0;
@@ -97,7 +97,7 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
                     const uint32_t dst = __builtin_popcount(e1) >= __builtin_popcount(e2)
                                              ? kBucketSlots * s1 + (uint32_t)__builtin_ctz(e1)
                                              : kBucketSlots * s2 + (uint32_t)__builtin_ctz(e2);
-                    const uint64_t emp = empty_entry(ekey, dst);
+                    const uint64_t emp = empty_entry<2>(ekey, dst);
                     if (atomicCAS((unsigned long long*)&table[dst], (unsigned long long)emp, (unsigned long long)e) ==
                         emp) {
                         table[T + lane] = 0ull;
@@ -153,7 +153,7 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
                 uint32_t h = kNone;
                 bool join = false;
                 if (e1 | e2) {
-                    h = claim_slot(e1, e2, b1, b2, x, hk.pick);
+                    h = claim_slot(e1, e2, 0u, b1, b2, 0u, x, hk.pick);
                 } else {
                     uint32_t fe = kNone;
                     for (uint32_t i = 0; i < kStash / 2; ++i) {
@@ -177,7 +177,7 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
                     break;
                 }
                 if (!join) {
-                    const uint64_t emp = empty_entry(ekey, h);
+                    const uint64_t emp = empty_entry<2>(ekey, h);
                     const uint64_t old =
                         atomicCAS((unsigned long long*)&table[h], (unsigned long long)emp, (unsigned long long)mine);
                     if (old == emp) {
@@ -223,7 +223,7 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
         //    with count 1, repeats add 1 to their value's new counter; claims
         //    past the prefix (the dropped item's among them) are released
         if (in && hit) atomicAdd(&words[2 * slot + 1], 1u);
-        if (newf) table[hp] = in ? make_entry(x, 1u) : empty_entry(ekey, hp);
+        if (newf) table[hp] = in ? make_entry(x, 1u) : empty_entry<2>(ekey, hp);
         const bool repeat = in && miss && !newf;
         if (ballot(repeat)) {
             wave_sync();
@@ -251,7 +251,7 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
                     const uint32_t s = b + j * kWave + lane;
                     if (live_tag(cv[j])) {
                         if (cv[j] == 1u) {
-                            table[s] = empty_entry(ekey, s);
+                            table[s] = empty_entry<2>(ekey, s);
                             freed += 1;
                             sfreed += s >= T ? 1u : 0u;
                         } else {

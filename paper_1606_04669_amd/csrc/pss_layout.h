@@ -44,15 +44,19 @@ constexpr uint32_t kMaxLdsTableSlots = 65536;
 #endif
 constexpr uint32_t kBucketSlots = PSS_BUCKET_SLOTS;
 // Hash slots per counter x16: 1.875 per counter up to k = 1024, 1.625 above
-// (a speed / memory trade that never changes results: at k = 500 and 2000
-// these are the largest tables with which 16 and 5 waves share a CU's LDS).
+// with two bucket choices, 1.3125 with three (a speed / memory trade that
+// never changes results: at k = 500 and 2000 these are the largest tables
+// with which 16 and 6 waves share a CU's LDS).
 #ifndef PSS_SLOTS_X16
 #define PSS_SLOTS_X16 26
 #endif
 #ifndef PSS_SLOTS_X16_SMALLK
 #define PSS_SLOTS_X16_SMALLK 30
 #endif
-// Overflow slots after the buckets, for items whose two buckets are full.
+#ifndef PSS_SLOTS_X16_THREE
+#define PSS_SLOTS_X16_THREE 21
+#endif
+// Overflow slots after the buckets, for items whose buckets are all full.
 constexpr uint32_t kStash = 64;
 // Streams hold fewer than kStreamBound items: a count word of a hash slot
 // keeps its top 128 values for the victims and claims of a window.
@@ -79,6 +83,14 @@ PSS_HD inline uint32_t sort_lanes_per_k(uint32_t k) {
     return next_pow2((k + 63) / 64);
 }
 
+// Buckets an item may live in: three for the LDS-state classes above
+// k = 1024 (a fuller table, so that more waves fit a CU's LDS, at one more
+// bucket read per lookup), two elsewhere.  The block kernels derive the same
+// number from their register class.
+PSS_HD inline uint32_t hash_choices(uint32_t k, bool global_state) {
+    return !global_state && sort_lanes_per_k(k) >= 32 ? 3u : 2u;
+}
+
 struct ChunkLayout {
     uint32_t k;
     uint32_t nbuckets;      // hash buckets of kBucketSlots slots
@@ -95,9 +107,13 @@ struct ChunkLayout {
     // err_stride words apart (a multiple of 32: each block starts a cache
     // line); err_bytes per error (4, or 2 / 1 by with_error_width)
     uint32_t err_stride, err_bytes;
+    uint32_t choices;  // buckets per item (hash_choices)
 
-    // Default hash slots per counter (x16).
-    PSS_HD static uint32_t default_slots_x16(uint32_t k) { return k <= 1024 ? PSS_SLOTS_X16_SMALLK : PSS_SLOTS_X16; }
+    // Default hash slots per counter (x16) for tables with `choices` buckets
+    // per item.
+    PSS_HD static uint32_t default_slots_x16(uint32_t k, uint32_t choices) {
+        return choices == 3 ? PSS_SLOTS_X16_THREE : k <= 1024 ? PSS_SLOTS_X16_SMALLK : PSS_SLOTS_X16;
+    }
 
     // slots_per_counter_x16: hash slots per counter (x16), a speed / memory
     // knob that never changes results (0 = default).  global_state selects
@@ -106,7 +122,8 @@ struct ChunkLayout {
         ChunkLayout L;
         L.k = k;
         L.global_state = global_state ? 1u : 0u;
-        if (slots_per_counter_x16 == 0) slots_per_counter_x16 = default_slots_x16(k);
+        L.choices = hash_choices(k, global_state);
+        if (slots_per_counter_x16 == 0) slots_per_counter_x16 = default_slots_x16(k, L.choices);
         uint32_t want = (uint32_t)(((uint64_t)k * slots_per_counter_x16 + 15) / 16);
         if (want < 256) want = 256;
         L.nbuckets = (want + kBucketSlots - 1) / kBucketSlots;
@@ -177,7 +194,7 @@ struct FreqLayout {
         FreqLayout L;
         L.k = k;
         L.counters = k - 1;
-        uint32_t want = (uint32_t)(((uint64_t)k * ChunkLayout::default_slots_x16(k) + 15) / 16);
+        uint32_t want = (uint32_t)(((uint64_t)k * ChunkLayout::default_slots_x16(k, 2) + 15) / 16);
         if (want < 256) want = 256;
         L.nbuckets = (want + kBucketSlots - 1) / kBucketSlots;
         L.tsize = kBucketSlots * L.nbuckets;

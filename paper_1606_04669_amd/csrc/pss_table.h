@@ -1,11 +1,12 @@
 // The block kernels' hash table of counters and their input staging, shared
 // by the Space Saving and the Frequent block kernels.
 //
-// A counter is a slot of a two-choice hash table: its 64-bit entry holds the
-// item id (low word) and the count (high word); count 0 marks an empty slot
-// and the top 128 count values are tags a window uses for victims and
-// claims.  An item lives in one of the 8-slot buckets its two hash functions
-// pick, or in a 64-slot stash after them when both are full.
+// A counter is a slot of a multiple-choice hash table: its 64-bit entry
+// holds the item id (low word) and the count (high word); count 0 marks an
+// empty slot and the top 128 count values are tags a window uses for
+// victims and claims.  An item lives in one of the 8-slot buckets its two
+// (or three) hash functions pick, or in a 64-slot stash after them when they
+// are all full.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -42,13 +43,13 @@ __device__ __forceinline__ uint64_t make_entry(uint32_t key, uint32_t tag) {
 // and the stash under them (possible for ids chosen to collide) is run again
 // from its start with other odd multipliers (SplitMix64 of the attempt).
 struct HashKeys {
-    uint32_t h1, h2, h3, pick;
+    uint32_t h1, h2, h3, pick, h4;
 };
 
 constexpr uint32_t kHashAttempts = 4;
 
 __device__ __forceinline__ HashKeys hash_keys(uint32_t attempt) {
-    if (attempt == 0) return HashKeys{0x9E3779B1u, 0x85EBCA77u, 0xC2B2AE3Du, 0x2C1B3C6Du};
+    if (attempt == 0) return HashKeys{0x9E3779B1u, 0x85EBCA77u, 0xC2B2AE3Du, 0x2C1B3C6Du, 0x27D4EB2Fu};
     uint64_t z = (uint64_t)attempt * 0x9E3779B97F4A7C15ull;
     uint64_t a = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     a = (a ^ (a >> 27)) * 0x94D049BB133111EBull;
@@ -56,7 +57,11 @@ __device__ __forceinline__ HashKeys hash_keys(uint32_t attempt) {
     uint64_t b = (a + 0x9E3779B97F4A7C15ull) * 0xBF58476D1CE4E5B9ull;
     b = (b ^ (b >> 27)) * 0x94D049BB133111EBull;
     b ^= b >> 31;
-    return HashKeys{(uint32_t)a | 1u, (uint32_t)(a >> 32) | 1u, (uint32_t)b | 1u, (uint32_t)(b >> 32) | 1u};
+    uint64_t c = (b + 0x9E3779B97F4A7C15ull) * 0xBF58476D1CE4E5B9ull;
+    c = (c ^ (c >> 27)) * 0x94D049BB133111EBull;
+    c ^= c >> 31;
+    return HashKeys{(uint32_t)a | 1u, (uint32_t)(a >> 32) | 1u, (uint32_t)b | 1u, (uint32_t)(b >> 32) | 1u,
+                    (uint32_t)c | 1u};
 }
 
 // The two buckets of an item: multiplicative hashes scaled to nb buckets;
@@ -72,30 +77,47 @@ __device__ __forceinline__ uint32_t alt_bucket(uint32_t x, uint32_t nb, uint32_t
     return b2 != b1 ? b2 : (b1 + 1 == nb ? 0u : b1 + 1);
 }
 
+// The third bucket of a three-choice table: a third multiplicative hash,
+// stepped past the first two buckets when it meets one of them (nb >= 3).
+__device__ __forceinline__ uint32_t third_bucket(uint32_t x, uint32_t nb, uint32_t b1, uint32_t b2,
+                                                 const HashKeys& hk) {
+    uint32_t h = x * hk.h4;
+    h = (h << 9) | (h >> 23);
+    uint32_t b = (uint32_t)(((uint64_t)(h * hk.h3) * nb) >> 32);
+    b = (b == b1 || b == b2) ? (b + 1 == nb ? 0u : b + 1) : b;
+    b = (b == b1 || b == b2) ? (b + 1 == nb ? 0u : b + 1) : b;
+    return b;
+}
+
 __device__ __forceinline__ bool live_tag(uint32_t tag) { return tag - 1u < kTagVict - 1u; }
 
 // Keys of empty bucket slots.  A lookup compares an item only with the keys
-// of its own two buckets, so an empty slot of bucket b may hold any id whose
-// two buckets both differ from b: no lookup that reads bucket b can match
-// it, and lookups need not test count words.  Id 0 has buckets 0 and 1 under
-// any multipliers (0 times anything is 0, and a second bucket equal to the
-// first moves to its neighbour), so empty slots of every bucket but 0 and 1
-// hold 0, and those of buckets 0 and 1 hold an id e1 whose two buckets are
-// neither.  (Stash slots are compared only while live; they keep 0.)
+// of its own buckets, so an empty slot of bucket b may hold any id whose
+// buckets all differ from b: no lookup that reads bucket b can match it,
+// and lookups need not test count words.  Id 0 has buckets 0 and 1 (and 2
+// with three choices) under any multipliers (0 times anything is 0, and a
+// later bucket equal to an earlier one steps to the next), so empty slots of
+// every other bucket hold 0, and those of the first NCH buckets hold an id
+// e1 whose buckets are none of them.  (Stash slots are compared only while
+// live; they keep 0.)
 //
 // e1 for nb buckets under hk, or 0 when none was found among the first ids
 // (the caller then treats the hash functions as unusable).
+template <int NCH>
 __device__ __forceinline__ uint32_t empty_key_e1(uint32_t nb, const HashKeys& hk) {
     for (uint32_t e1 = 1u; e1 < 1024u; ++e1) {
         const uint32_t c = home_bucket(e1, nb, hk), d = alt_bucket(e1, nb, c, hk);
-        if (c > 1u && d > 1u) return e1;
+        bool ok = c >= (uint32_t)NCH && d >= (uint32_t)NCH;
+        if constexpr (NCH == 3) ok = ok && third_bucket(e1, nb, c, d, hk) >= 3u;
+        if (ok) return e1;
     }
     return 0u;
 }
 
 // The entry of an empty slot s.
+template <int NCH>
 __device__ __forceinline__ uint64_t empty_entry(uint32_t e1, uint32_t s) {
-    return s < 2u * kBucketSlots ? (uint64_t)e1 : 0ull;
+    return s < (uint32_t)NCH * kBucketSlots ? (uint64_t)e1 : 0ull;
 }
 
 // One bucket: kBucketSlots key/tag pairs, read with kBucketSlots / 2
@@ -174,13 +196,17 @@ __device__ __forceinline__ uint32_t pick_free(uint32_t e, uint32_t x, uint32_t m
     return base + ((r >= (e & 1u)) ? 1u : 0u);
 }
 
-// The slot a missing item claims: a free slot of the emptier of its two
-// buckets (the first on ties), chosen by pick_free; kNone when both are full.
-__device__ __forceinline__ uint32_t claim_slot(uint32_t e1, uint32_t e2, uint32_t b1, uint32_t b2, uint32_t x,
-                                               uint32_t mult) {
-    const bool first = __builtin_popcount(e1) >= __builtin_popcount(e2);
-    const uint32_t e = first ? e1 : e2;
-    const uint32_t b = first ? b1 : b2;
+// The slot a missing item claims: a free slot of the emptiest of its
+// buckets (the earliest on ties), chosen by pick_free; kNone when all are
+// full.  Two choices: e3 = 0.
+__device__ __forceinline__ uint32_t claim_slot(uint32_t e1, uint32_t e2, uint32_t e3, uint32_t b1, uint32_t b2,
+                                               uint32_t b3, uint32_t x, uint32_t mult) {
+    const uint32_t n1 = __builtin_popcount(e1), n2 = __builtin_popcount(e2), n3 = __builtin_popcount(e3);
+    const bool first = n1 >= n2;
+    uint32_t e = first ? e1 : e2, b = first ? b1 : b2;
+    const bool third = n3 > (first ? n1 : n2);
+    e = third ? e3 : e;
+    b = third ? b3 : b;
     return e ? kBucketSlots * b + pick_free(e, x, mult) : kNone;
 }
 

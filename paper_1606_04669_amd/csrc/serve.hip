@@ -232,7 +232,7 @@ int run_launch(pss_server* srv, uint32_t si) {
             h.d.out = 0;
             h.d.eoff = 0;
             h.d.k = k;
-            h.d.slots_x16 = ChunkLayout::default_slots_x16(k);
+            h.d.slots_x16 = ChunkLayout::default_slots_x16(k, hash_choices(k, false));
             h.cls = class_of(k);
             h.req = r;
             h.c = c;

@@ -277,10 +277,28 @@ __device__ __forceinline__ void load_lane(uint2& a, const uint32_t* __restrict__
     a = load2(items, tile + 2 * lane, n, stop, vec_ok);
 }
 
+__device__ __forceinline__ void load_lane_whole(uint4& a, const uint32_t* __restrict__ items, uint64_t tile,
+                                                uint32_t lane) {
+    const u32x4_t t = PSS_NT_LOAD((const u32x4_t*)(items + tile) + lane);
+    a = make_uint4(t[0], t[1], t[2], t[3]);
+}
+
+__device__ __forceinline__ void load_lane_whole(uint2& a, const uint32_t* __restrict__ items, uint64_t tile,
+                                                uint32_t lane) {
+    const u32x2_t t = PSS_NT_LOAD((const u32x2_t*)(items + tile) + lane);
+    a = make_uint2(t[0], t[1]);
+}
+
 __device__ __forceinline__ Prefetch fetch_half(const uint32_t* __restrict__ items, uint64_t tile, uint64_t n,
                                                uint64_t stop, int vec_ok, uint32_t lane) {
     Prefetch p;
-    load_lane(p.a, items, tile, n, stop, vec_ok, lane);
+    if (vec_ok && tile + kRingHalf <= stop) {
+        // the whole half is in the block (stop <= n): one load per lane, no
+        // per-lane bounds (a wave-uniform test)
+        load_lane_whole(p.a, items, tile, lane);
+    } else {
+        load_lane(p.a, items, tile, n, stop, vec_ok, lane);
+    }
     return p;
 }
 

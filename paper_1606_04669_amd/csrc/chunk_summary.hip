@@ -704,7 +704,7 @@ __device__ __forceinline__ uint64_t build_level_global(unsigned char* sb, unsign
 // item found no free slot under the hash functions hk (the caller runs the
 // block again with other ones); else kDone.
 constexpr uint32_t kDone = 0, kOverflow = 1;
-template <int P, bool G>
+template <int P, bool G, bool EB = false>
 __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__ items, uint64_t n, uint64_t begin,
                                                     uint64_t end, const ChunkLayout& L, int vec_ok, unsigned char* sb,
                                                     unsigned char* lds, uint32_t* __restrict__ errs,
@@ -725,8 +725,9 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
     const SlotIds ids{table};
     uint32_t* ring = (uint32_t*)(lds + L.off_ring);
     const uint4* stash4 = tbl4 + T / 2;
-    // the block's error scratch at the layout's width
-    const uint32_t ew = L.err_bytes;
+    // the block's error scratch at the layout's width (EB: 1 byte, known at
+    // compile time, so the window loop has no width switch)
+    const uint32_t ew = EB ? 1u : L.err_bytes;
     auto err_put = [&](uint32_t s, uint32_t e) {
         if (ew == 1)
             ((uint8_t*)errs)[s] = (uint8_t)e;
@@ -1184,7 +1185,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
 
 // A block under the attempts' hash functions in turn; after the last one
 // overflows, the block is marked failed (the caller sees a device error).
-template <int P, bool G>
+template <int P, bool G, bool EB = false>
 __device__ __forceinline__ void summarize_block_any(const uint32_t* __restrict__ items, uint64_t n, uint64_t begin,
                                                     uint64_t end, const ChunkLayout& L, int vec_ok,
                                                     unsigned char* sb, unsigned char* lds,
@@ -1192,8 +1193,8 @@ __device__ __forceinline__ void summarize_block_any(const uint32_t* __restrict__
                                                     uint32_t* __restrict__ o_cnt, uint32_t* __restrict__ o_err,
                                                     uint32_t* __restrict__ o_size, uint32_t* __restrict__ o_min) {
     for (uint32_t attempt = 0; attempt < kHashAttempts; ++attempt) {
-        if (summarize_block<P, G>(items, n, begin, end, L, vec_ok, sb, lds, errs, o_item, o_cnt, o_err, o_size, o_min,
-                                  hash_keys(attempt)) == kDone)
+        if (summarize_block<P, G, EB>(items, n, begin, end, L, vec_ok, sb, lds, errs, o_item, o_cnt, o_err, o_size,
+                                      o_min, hash_keys(attempt)) == kDone)
             return;
         wave_sync();  // the next attempt clears the table this one used
     }
@@ -1205,8 +1206,9 @@ __device__ __forceinline__ void summarize_block_any(const uint32_t* __restrict__
 
 // One wave per block c of C: [floor(c n / C), floor((c+1) n / C)) (Algorithm
 // 1's block bounds, 64-bit products, n < 2^32).  G: state slab gstate +
-// c * state_bytes.  Error scratch of block c: errs + c * err_stride.
-template <int P, bool G>
+// c * state_bytes.  Error scratch of block c: errs + c * err_stride.  EB:
+// the layout stores errors in 1 byte.
+template <int P, bool G, bool EB>
 __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __restrict__ items, uint64_t n,
                                                            uint32_t chunks, ChunkLayout L, int vec_ok,
                                                            uint32_t* __restrict__ o_item,
@@ -1222,8 +1224,8 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
     const uint64_t begin = (uint64_t)c * n / chunks;
     const uint64_t end = (uint64_t)(c + 1) * n / chunks;
     const uint64_t ob = (uint64_t)c * L.k;
-    summarize_block_any<P, G>(items, n, begin, end, L, vec_ok, sb, smem, errs + (size_t)c * L.err_stride, o_item + ob,
-                          o_cnt + ob, o_err + ob, o_size + c, o_min + c);
+    summarize_block_any<P, G, EB>(items, n, begin, end, L, vec_ok, sb, smem, errs + (size_t)c * L.err_stride,
+                                  o_item + ob, o_cnt + ob, o_err + ob, o_size + c, o_min + c);
 }
 
 // Batched form: every wave of a persistent grid takes blocks from a queue
@@ -1313,15 +1315,28 @@ extern "C" int pss_debug_kstats(unsigned long long* out, int reset) {
 }
 #endif
 
+template <int P, bool G, bool EB>
+static hipError_t launch_pe(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L, int vec_ok,
+                            const BlockSummaries& out, unsigned char* gstate, uint32_t* errs, hipStream_t stream) {
+    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
+    hipFuncSetAttribute((const void*)chunk_summary_kernel<P, G, EB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)L.lds_bytes);
+    hipLaunchKernelGGL((chunk_summary_kernel<P, G, EB>), dim3(chunks), dim3(64), L.lds_bytes, stream, d_items, n,
+                       chunks, L, vec_ok, out.item, out.cnt, out.err, out.size, out.min, gstate, errs);
+    return hipGetLastError();
+}
+
+// 1-byte errors (the common case: blocks below 255 k items) get their own
+// instance of the LDS-state kernels up to k = 1024, which issue VALU
+// instructions most of the time (2% faster there; the k = 2000 instance,
+// bound by latency, gains nothing from it)
 template <int P, bool G>
 static hipError_t launch_p(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L, int vec_ok,
                            const BlockSummaries& out, unsigned char* gstate, uint32_t* errs, hipStream_t stream) {
-    (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
-    hipFuncSetAttribute((const void*)chunk_summary_kernel<P, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)L.lds_bytes);
-    hipLaunchKernelGGL((chunk_summary_kernel<P, G>), dim3(chunks), dim3(64), L.lds_bytes, stream, d_items, n, chunks,
-                       L, vec_ok, out.item, out.cnt, out.err, out.size, out.min, gstate, errs);
-    return hipGetLastError();
+    if constexpr (!G && P < 32) {
+        if (L.err_bytes == 1) return launch_pe<P, G, true>(d_items, n, chunks, L, vec_ok, out, gstate, errs, stream);
+    }
+    return launch_pe<P, G, false>(d_items, n, chunks, L, vec_ok, out, gstate, errs, stream);
 }
 
 // Waves per CU for blocks whose state lives in device memory.  Their table

@@ -514,7 +514,7 @@ def frequent_leg(B, ctx, streams, dev, ks, steps: int):
     kms = {}
     for st, d in zip(streams, dev):
         for k in ks:
-            C = ctx.plan_chunks(n, k)
+            C = ctx.frequent_plan_chunks(n, k)
             B.pss_frequent_run(ctx, d, k=k, chunks=C, stream=stream)  # warm-up (allocates)
             ctx.timing(True)
             ctx.phase_times(reset=True)
@@ -540,7 +540,7 @@ def frequent_leg(B, ctx, streams, dev, ks, steps: int):
     dom_ms = kms[dom_k][0] / max(1, kms[dom_k][1])
     ach = 4.0 * n / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
     return {"workload": "the plain-large streams and k with the Frequent summary (k - 1 counters), "
-                        "the planner's chunk count",
+                        "the Frequent planner's chunk count",
             "g_items_per_s": round(total_items / total_s / 1e9, 3), "cases": cases,
             "roofline": {"bound": "hbm", "kernel": "frequent_block_kernel, k=%d" % dom_k, "achieved": round(ach, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),

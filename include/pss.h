@@ -232,8 +232,14 @@ int pss_test_fold_failed_block(pss_summary* s, uint64_t n, void* stream);
  * merges and report in LDS); 0 for a null ctx. */
 uint32_t pss_frequent_max_k(const pss_ctx* ctx);
 
+/* Chunk count pss_frequent_run picks for n items and k counters when given
+ * chunks = 0: pss_plan_chunks' rule applied to the Frequent block kernel,
+ * whose per-block LDS footprint differs (a deterministic function of n, k
+ * and the device; 1 for a null ctx). */
+uint32_t pss_frequent_plan_chunks(const pss_ctx* ctx, uint64_t n, uint32_t k);
+
 /* Parallel Frequent over the device array d_items[0, n), k - 1 counters per
- * block, C = chunks blocks (0: pss_plan_chunks).  kind PSS_Q_MAJORITY: the
+ * block, C = chunks blocks (0: pss_frequent_plan_chunks).  kind PSS_Q_MAJORITY: the
  * entries with (count + D) * k > n (every true k-majority item is among
  * them), PSS_ETRUNC with *n_out = required when more than cap; kind
  * PSS_Q_TOPK: the first min(cap, size) entries of the merged summary.  Order:

@@ -105,6 +105,8 @@ def lib():
         L.pss_read_bandwidth.argtypes = [vp, vp, u64, u32, vp, ctypes.POINTER(ctypes.c_double)]
         L.pss_frequent_max_k.restype = u32
         L.pss_frequent_max_k.argtypes = [vp]
+        L.pss_frequent_plan_chunks.restype = u32
+        L.pss_frequent_plan_chunks.argtypes = [vp, u64, u32]
         L.pss_frequent_run.argtypes = [vp, vp, u64, u32, u32, i32, vp, u32, u32p, u64p, u32p, vp]
         L.pss_frequent_block_summaries.argtypes = [vp, vp, u64, u32, u32, u32p, u32, vp, u32p, u64p, vp]
         L.pss_tune_chunks.argtypes = [vp, vp, u64, u32, vp, u32p, ctypes.POINTER(ctypes.c_double)]
@@ -237,6 +239,9 @@ class Context:
     @property
     def frequent_max_k(self) -> int:
         return int(lib().pss_frequent_max_k(self.handle))
+
+    def frequent_plan_chunks(self, n: int, k: int) -> int:
+        return int(lib().pss_frequent_plan_chunks(self.handle, n, k))
 
     def set_budget(self, nbytes: int):
         """Device bytes the context's workspaces may hold in all (0 = no limit)."""

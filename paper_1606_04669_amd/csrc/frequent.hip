@@ -14,7 +14,7 @@
 //
 // The block kernel reads its block in windows of up to 64 items, one per
 // lane, looked up against the counters at window start (the Space Saving
-// kernel's two-choice table).  Hits commute.  New items (first occurrences
+// kernel's multiple-choice table).  Hits commute.  New items (first occurrences
 // of unmonitored values) take free counters in window order; the first new
 // item beyond the free counters is a decrement step, so the wave applies the
 // window up to it, decrements every counter (one pass over the table, at
@@ -32,11 +32,12 @@ namespace {
 extern __shared__ __align__(16) unsigned char smem[];
 
 // Sequential Frequent over items[begin, end) by one wave, k - 1 counters in
-// the hash table at `tbl` (LDS).  Returns kOverflow when a new item found no
-// free slot under the hash functions hk (nothing written), else writes the
-// summary (entries, size, D) and returns kDone.
+// the hash table at `tbl` (LDS), NCH buckets per item.  Returns kOverflow
+// when a new item found no free slot under the hash functions hk (nothing
+// written), else writes the summary (entries, size, D) and returns kDone.
 constexpr uint32_t kFqDone = 0, kFqOverflow = 1;
 
+template <int NCH>
 __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ items, uint64_t n, uint64_t begin,
                                                    uint64_t end, const FreqLayout& L, int vec_ok,
                                                    unsigned char* lds, uint32_t* __restrict__ o_item,
@@ -54,9 +55,14 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
     const uint4* stash4 = tbl4 + T / 2;
     uint32_t* ring = (uint32_t*)(lds + L.off_ring);
 
-    const uint32_t ekey = uniform(empty_key_e1<2>(NB, hk));  // key of empty slots in buckets 0 and 1
+    // the item's third bucket, or none (its mask stays 0)
+    auto bucket3 = [&](uint32_t y, uint32_t c1, uint32_t c2) -> uint32_t {
+        if constexpr (NCH == 3) return third_bucket(y, NB, c1, c2, hk);
+        return 0u;
+    };
+    const uint32_t ekey = uniform(empty_key_e1<NCH>(NB, hk));  // key of empty slots in the first NCH buckets
     if (ekey == 0u) return kFqOverflow;  // unusable hash functions: the caller tries others
-    for (uint32_t i = lane; i < S; i += kWave) table[i] = empty_entry<2>(ekey, i);
+    for (uint32_t i = lane; i < S; i += kWave) table[i] = empty_entry<NCH>(ekey, i);
 
     // wave-uniform state (readfirstlane-anchored, see the Space Saving kernel)
     uint32_t size = 0, dec = 0, failed = 0, stash_live = 0;
@@ -90,14 +96,23 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
             slive = live_tag((uint32_t)(e >> 32));
             if (ballot(slive)) {
                 const uint32_t s1 = home_bucket(skey, NB, hk), s2 = alt_bucket(skey, NB, s1, hk);
+                const uint32_t s3 = bucket3(skey, s1, s2);
                 const Bucket B1 = load_bucket(tbl4, s1), B2 = load_bucket(tbl4, s2);
                 const uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2);
+                uint32_t e3 = 0u;
+                if constexpr (NCH == 3) e3 = empty_mask(load_bucket(tbl4, s3));
                 bool moved = false;
-                if (slive && (e1 | e2)) {
-                    const uint32_t dst = __builtin_popcount(e1) >= __builtin_popcount(e2)
-                                             ? kBucketSlots * s1 + (uint32_t)__builtin_ctz(e1)
-                                             : kBucketSlots * s2 + (uint32_t)__builtin_ctz(e2);
-                    const uint64_t emp = empty_entry<2>(ekey, dst);
+                if (slive && (e1 | e2 | e3)) {
+                    // the emptiest bucket (the earliest on ties), its first free slot
+                    const uint32_t n1 = __builtin_popcount(e1), n2 = __builtin_popcount(e2);
+                    const bool first = n1 >= n2;
+                    uint32_t fm = first ? e1 : e2, fb = first ? s1 : s2;  // free-slot mask, bucket
+                    if (__builtin_popcount(e3) > (first ? n1 : n2)) {
+                        fm = e3;
+                        fb = s3;
+                    }
+                    const uint32_t dst = kBucketSlots * fb + (uint32_t)__builtin_ctz(fm);
+                    const uint64_t emp = empty_entry<NCH>(ekey, dst);
                     if (atomicCAS((unsigned long long*)&table[dst], (unsigned long long)emp, (unsigned long long)e) ==
                         emp) {
                         table[T + lane] = 0ull;
@@ -119,12 +134,18 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
         uint32_t slot = 0, hp = kNone;
         const uint32_t b1 = home_bucket(x, NB, hk);
         const uint32_t b2 = alt_bucket(x, NB, b1, hk);
+        const uint32_t b3 = bucket3(x, b1, b2);
         Bucket B1 = load_bucket(tbl4, b1), B2 = load_bucket(tbl4, b2);
+        Bucket B3;
+        if constexpr (NCH == 3) B3 = load_bucket(tbl4, b3);
         {
             const uint32_t h1 = match_mask(B1, x), h2 = match_mask(B2, x);
-            slot = h1 ? kBucketSlots * b1 + (uint32_t)__builtin_ctz(h1)
-                      : kBucketSlots * b2 + ((uint32_t)__builtin_ctz(h2 | (1u << kBucketSlots)) & (kBucketSlots - 1));
-            hit = valid && (h1 | h2) != 0u;
+            uint32_t h3 = 0u;
+            if constexpr (NCH == 3) h3 = match_mask(B3, x);
+            const uint32_t hb = h1 ? b1 : h2 ? b2 : b3;
+            const uint32_t hm = h1 ? h1 : h2 ? h2 : h3;
+            slot = kBucketSlots * hb + ((uint32_t)__builtin_ctz(hm | (1u << kBucketSlots)) & (kBucketSlots - 1));
+            hit = valid && (h1 | h2 | h3) != 0u;
         }
         for (uint64_t sm = ballot(slive); sm; sm &= sm - 1) {
             const uint32_t j = (uint32_t)__builtin_ctzll(sm);
@@ -147,13 +168,14 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
         //    a lost swap to another value removes the slot from the view
         if (miss) {
             const uint64_t mine = make_entry(x, kTagPend + lane);
-            uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2);
+            uint32_t e1 = empty_mask(B1), e2 = empty_mask(B2), e3 = 0u;
+            if constexpr (NCH == 3) e3 = empty_mask(B3);
             uint32_t steps = 0;
             for (;;) {
                 uint32_t h = kNone;
                 bool join = false;
-                if (e1 | e2) {
-                    h = claim_slot(e1, e2, 0u, b1, b2, 0u, x, hk.pick);
+                if (e1 | e2 | e3) {
+                    h = claim_slot(e1, e2, e3, b1, b2, b3, x, hk.pick);
                 } else {
                     uint32_t fe = kNone;
                     for (uint32_t i = 0; i < kStash / 2; ++i) {
@@ -177,7 +199,7 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
                     break;
                 }
                 if (!join) {
-                    const uint64_t emp = empty_entry<2>(ekey, h);
+                    const uint64_t emp = empty_entry<NCH>(ekey, h);
                     const uint64_t old =
                         atomicCAS((unsigned long long*)&table[h], (unsigned long long)emp, (unsigned long long)mine);
                     if (old == emp) {
@@ -185,9 +207,15 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
                         break;
                     }
                     join = (uint32_t)old == x && (uint32_t)(old >> 32) >= kTagPend;
-                    if (!join && h < T) {
+                    if (!join && h < T) {  // taken by another value
                         const uint32_t bit = 1u << (h % kBucketSlots);
-                        if (h / kBucketSlots == b1) e1 &= ~bit; else e2 &= ~bit;
+                        const uint32_t hb = h / kBucketSlots;
+                        if (hb == b1)
+                            e1 &= ~bit;
+                        else if (hb == b2)
+                            e2 &= ~bit;
+                        else
+                            e3 &= ~bit;
                     }
                 }
                 if (join) {
@@ -195,7 +223,7 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
                     hp = h;
                     break;
                 }
-                if (++steps > 2 * kBucketSlots + kStash) {
+                if (++steps > (uint32_t)NCH * kBucketSlots + kStash) {
                     bad = true;
                     break;
                 }
@@ -223,7 +251,7 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
         //    with count 1, repeats add 1 to their value's new counter; claims
         //    past the prefix (the dropped item's among them) are released
         if (in && hit) atomicAdd(&words[2 * slot + 1], 1u);
-        if (newf) table[hp] = in ? make_entry(x, 1u) : empty_entry<2>(ekey, hp);
+        if (newf) table[hp] = in ? make_entry(x, 1u) : empty_entry<NCH>(ekey, hp);
         const bool repeat = in && miss && !newf;
         if (ballot(repeat)) {
             wave_sync();
@@ -251,7 +279,7 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
                     const uint32_t s = b + j * kWave + lane;
                     if (live_tag(cv[j])) {
                         if (cv[j] == 1u) {
-                            table[s] = empty_entry<2>(ekey, s);
+                            table[s] = empty_entry<NCH>(ekey, s);
                             freed += 1;
                             sfreed += s >= T ? 1u : 0u;
                         } else {
@@ -303,6 +331,7 @@ __device__ __forceinline__ uint32_t frequent_block(const uint32_t* __restrict__ 
 }
 
 // One wave per block c of C (Algorithm 1's bounds, 64-bit products).
+template <int NCH>
 __global__ __launch_bounds__(64) void frequent_block_kernel(const uint32_t* __restrict__ items, uint64_t n,
                                                             uint32_t chunks, FreqLayout L, int vec_ok,
                                                             BlockSummaries out) {
@@ -311,7 +340,7 @@ __global__ __launch_bounds__(64) void frequent_block_kernel(const uint32_t* __re
     const uint64_t end = (uint64_t)(c + 1) * n / chunks;
     const uint64_t ob = (uint64_t)c * L.k;
     for (uint32_t attempt = 0; attempt < kHashAttempts; ++attempt) {
-        if (frequent_block(items, n, begin, end, L, vec_ok, smem, out.item + ob, out.cnt + ob, out.err + ob,
+        if (frequent_block<NCH>(items, n, begin, end, L, vec_ok, smem, out.item + ob, out.cnt + ob, out.err + ob,
                            out.size + c, out.min + c, hash_keys(attempt)) == kFqDone)
             return;
         wave_sync();
@@ -499,10 +528,16 @@ hipError_t launch_frequent_blocks(const uint32_t* d_items, uint64_t n, uint32_t 
                                   const BlockSummaries& out, hipStream_t stream) {
     (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
     const int vec_ok = ((uintptr_t)d_items & 15u) == 0;
-    hipFuncSetAttribute((const void*)frequent_block_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)L.lds_bytes);
-    hipLaunchKernelGGL(frequent_block_kernel, dim3(chunks), dim3(64), L.lds_bytes, stream, d_items, n, chunks, L,
-                       vec_ok, out);
+    auto launch = [&](auto kern) {
+        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
+        hipLaunchKernelGGL(kern, dim3(chunks), dim3(64), L.lds_bytes, stream, d_items, n, chunks, L, vec_ok, out);
+    };
+    if (L.choices == 3)
+        launch(frequent_block_kernel<3>);
+    else if (L.choices == 2)
+        launch(frequent_block_kernel<2>);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -34,22 +34,35 @@ constexpr uint64_t kPlanRounds = PSS_PLAN_ROUNDS;
 namespace pss {
 thread_local int t_last_device_error = 0;
 
+namespace {
+// Blocks for n items and k counters when per_cu block waves fit a CU at once:
+// enough resident waves to cover every CU a few times over, while keeping
+// blocks long next to k (the reduction tree moves ~C*k entries).
+uint64_t plan_for_residency(int cu_count, uint64_t per_cu, uint64_t n, uint32_t k) {
+    per_cu = std::min<uint64_t>(std::max<uint64_t>(per_cu, 1), 32);  // 32 waves per CU at most
+    // many resident waves (small k): twice the rounds, the tree stays cheap
+    const uint64_t want = (uint64_t)std::max(cu_count, 1) * per_cu * (per_cu >= 8 ? 2 * kPlanRounds : kPlanRounds);
+    uint64_t cap_len = n / (16ull * k);
+    if (cap_len < 1) cap_len = 1;
+    return std::min(want, cap_len);
+}
+}  // namespace
+
 uint32_t plan_chunks(int cu_count, size_t lds_per_cu, size_t lds_max, uint64_t n, uint32_t k) {
     if (n == 0 || k < 2) return 1;
     if (k > kMaxK) k = kMaxK;
-    // enough resident waves to cover every CU a few times over, while keeping
-    // blocks long next to k (the reduction tree moves ~C*k entries)
     const ChunkLayout L = chunk_layout(k, lds_max);
-    uint64_t per_cu = lds_waves(lds_per_cu, L.lds_bytes);
-    per_cu = std::min<uint64_t>(std::max<uint64_t>(per_cu, 1), 32);  // 32 waves per CU at most
-    // many resident waves (small k): twice the rounds, the tree stays cheap
-    uint64_t want = (uint64_t)std::max(cu_count, 1) * per_cu * (per_cu >= 8 ? 2 * kPlanRounds : kPlanRounds);
-    uint64_t cap_len = n / (16ull * k);
-    if (cap_len < 1) cap_len = 1;
-    uint64_t c = std::min(want, cap_len);
+    uint64_t c = plan_for_residency(cu_count, lds_waves(lds_per_cu, L.lds_bytes), n, k);
     if (L.global_state) c = std::min<uint64_t>(c, kStateBudget / (L.state_bytes + 4ull * L.err_stride));
     c = std::min<uint64_t>(c, kMaxChunks);
     return (uint32_t)std::max<uint64_t>(c, 1);
+}
+
+uint32_t plan_frequent_chunks(int cu_count, size_t lds_per_cu, uint64_t n, uint32_t k) {
+    if (n == 0 || k < 2) return 1;
+    if (k > kMaxK) k = kMaxK;
+    const uint64_t c = plan_for_residency(cu_count, lds_waves(lds_per_cu, FreqLayout::make(k).lds_bytes), n, k);
+    return (uint32_t)std::max<uint64_t>(std::min<uint64_t>(c, kMaxChunks), 1);
 }
 }  // namespace pss
 
@@ -336,6 +349,11 @@ uint32_t pss_plan_chunks(const pss_ctx* ctx, uint64_t n, uint32_t k) {
     return pss::plan_chunks(ctx->cu_count, ctx->lds_per_cu, ctx->lds_max, n, k);
 }
 
+uint32_t pss_frequent_plan_chunks(const pss_ctx* ctx, uint64_t n, uint32_t k) {
+    if (!ctx) return 1;
+    return pss::plan_frequent_chunks(ctx->cu_count, ctx->lds_per_cu, n, k);
+}
+
 int pss_tune_chunks(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t k, void* stream,
                     uint32_t* best_chunks, double* best_ms) {
     if (!ctx || !d_items || !best_chunks) return PSS_EINVAL;
@@ -597,7 +615,7 @@ int pss_frequent_run(pss_ctx* ctx, const uint32_t* d_items, uint64_t n, uint32_t
     if (kind != PSS_Q_MAJORITY && kind != PSS_Q_TOPK) return PSS_EINVAL;
     if (k < 2 || (uint64_t)k > n || n >= kStreamBound) return PSS_ERANGE;
     if (!frequent_k_fits(ctx, k)) return PSS_ERANGE;
-    const uint32_t C = chunks ? chunks : pss_plan_chunks(ctx, n, k);
+    const uint32_t C = chunks ? chunks : pss_frequent_plan_chunks(ctx, n, k);
     if (C > kMaxChunks) return PSS_ERANGE;
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;

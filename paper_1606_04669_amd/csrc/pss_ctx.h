@@ -54,6 +54,9 @@ struct DeviceGuard {
 // Chunk count for n items and k counters on a device with these
 // properties (pss_plan_chunks).
 uint32_t plan_chunks(int cu_count, size_t lds_per_cu, size_t lds_max, uint64_t n, uint32_t k);
+// The same for the Frequent block kernel, from its own LDS footprint
+// (pss_frequent_plan_chunks).
+uint32_t plan_frequent_chunks(int cu_count, size_t lds_per_cu, uint64_t n, uint32_t k);
 
 // The HIP error behind the last PSS_EDEVICE returned on this thread.
 extern thread_local int t_last_device_error;

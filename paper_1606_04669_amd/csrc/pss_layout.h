@@ -189,12 +189,14 @@ struct FreqLayout {
     uint32_t k, counters;
     uint32_t nbuckets, tsize, slots;
     uint32_t off_table, off_ring, lds_bytes;
+    uint32_t choices;  // buckets per item, as in the Space Saving table of the same k
 
     PSS_HD static FreqLayout make(uint32_t k) {
         FreqLayout L;
         L.k = k;
         L.counters = k - 1;
-        uint32_t want = (uint32_t)(((uint64_t)k * ChunkLayout::default_slots_x16(k, 2) + 15) / 16);
+        L.choices = hash_choices(k, false);
+        uint32_t want = (uint32_t)(((uint64_t)k * ChunkLayout::default_slots_x16(k, L.choices) + 15) / 16);
         if (want < 256) want = 256;
         L.nbuckets = (want + kBucketSlots - 1) / kBucketSlots;
         L.tsize = kBucketSlots * L.nbuckets;

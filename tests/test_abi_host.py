@@ -67,6 +67,10 @@ def test_strerror_and_null_handling_without_gpu(lib):
     assert lib.pss_batch_run(None, 0, None, None, None) == -1
     lib.pss_batch_destroy.argtypes = [ctypes.c_void_p]
     lib.pss_batch_destroy(None)
+    for f in (lib.pss_plan_chunks, lib.pss_frequent_plan_chunks):
+        f.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32]
+        f.restype = ctypes.c_uint32
+        assert f(None, 1 << 30, 2000) == 1
 
 
 def test_binding_names_match_the_abi():

@@ -1,8 +1,8 @@
 """GPU parity of the Frequent (Misra-Gries) path against its oracle,
 bit-exact: block summaries (entries and D), the merged summary, the report,
 on the hand-worked examples, seeded Zipf, uniform and adversarial streams,
-random small cases with ragged blocks and C > n, ids that overflow one
-bucket pair, and full size with the planner's C."""
+random small cases with ragged blocks and C > n, ids that overflow their
+buckets (two or three per item), and full size with the planner's C."""
 import json
 import os
 import random
@@ -107,13 +107,17 @@ def test_random_small_cases(B, ctx):
         check_all(B, ctx, items, k, C)
 
 
-def test_colliding_ids(B, ctx):
+@pytest.mark.parametrize("k,distinct,chunks", [(100, 300, 3), (1500, 60, 2), (1500, 300, 1)])
+def test_colliding_ids(B, ctx, k, distinct, chunks):
+    # ids whose buckets are all among the first two (k = 100) or three
+    # (k = 1500) of the table: they fill them and the stash, and past that the
+    # block retries under other hash functions
     from test_gpu_collisions import colliding_ids
-    ids = colliding_ids(100, 300)
+    ids = colliding_ids(k, distinct)
     rng = np.random.default_rng(3)
-    items = np.concatenate([np.tile(ids, 40), ids[rng.zipf(1.3, 20000).clip(1, 300) - 1]]).astype(np.uint32)
-    say("frequent colliding ids n=%d" % len(items))
-    check_all(B, ctx, items, 100, 3)
+    items = np.concatenate([np.tile(ids, 40), ids[rng.zipf(1.3, 20000).clip(1, distinct) - 1]]).astype(np.uint32)
+    say("frequent colliding ids k=%d distinct=%d n=%d" % (k, distinct, len(items)))
+    check_all(B, ctx, items, k, chunks)
 
 
 def test_planted_majority_k2(B, ctx):
@@ -131,7 +135,7 @@ def test_full_size_end_to_end(B, ctx):
     d = torch.from_numpy(items.view(np.int32)).to("cuda")
     threads = max(1, min(16, os.cpu_count() or 1))
     for k in (500, 2000):
-        C = ctx.plan_chunks(n, k)
+        C = ctx.frequent_plan_chunks(n, k)
         say("frequent full size k=%d C=%d" % (k, C))
         whole, dd, used = B.pss_frequent_run(ctx, d, k=k, chunks=C, kind=B.PSS_Q_TOPK)
         want = O.frequent_summary_threads(items, k, C, threads)

@@ -53,6 +53,16 @@ int main() {
     for (unsigned b : {1u, 1280u, 1281u, 11520u, 11600u, 32000u, 32608u})
         printf("%u ", lds_waves(163840, b));
     printf("\n");
+    // the Frequent block layout beside the Space Saving one of the same k
+    auto emit_freq = [](unsigned k) {
+        const FreqLayout F = FreqLayout::make(k);
+        const ChunkLayout L = ChunkLayout::make(k, false);
+        printf("%u %u %u %u %u %u %u %u %u ", k, F.choices, L.choices, F.nbuckets, L.nbuckets, F.slots,
+               F.off_ring, F.lds_bytes, lds_waves(163840, F.lds_bytes));
+    };
+    for (unsigned k = 2; k <= 8192; k += k < 600 ? 1 : 37) emit_freq(k);
+    for (unsigned k : {1000u, 1024u, 1025u, 2000u, 2048u, 4096u}) emit_freq(k);
+    printf("\n");
     return 0;
 }
 """
@@ -75,6 +85,9 @@ def layouts(tmp_path_factory):
     consts = [int(v) for v in out[2].split()]
     c.update(zip(["bucket", "stash", "hist", "bound", "ring", "unit"], consts))
     c["waves"] = [int(v) for v in out[3].split()]
+    f = [int(v) for v in out[4].split()]
+    c["freq"] = [dict(zip(["k", "ch", "ch_ss", "nb", "nb_ss", "slots", "ring", "lds", "waves"], f[i:i + 9]))
+                 for i in range(0, len(f), 9)]
     return json.loads(out[0]), c
 
 
@@ -166,3 +179,20 @@ def test_three_bucket_choices_only_for_the_large_lds_classes(layouts):
         assert r["ch"] == want, r
         # every item has that many distinct buckets beyond the ones id 0 takes
         assert r["nb"] > r["ch"]
+
+
+def test_frequent_layout_shares_the_table_shape(layouts):
+    # the Frequent block kernel uses the Space Saving table of the same k:
+    # the same buckets per item and bucket count, the 64-slot stash after
+    # them, the 8-byte entries before the ring
+    _, c = layouts
+    for r in c["freq"]:
+        assert r["ch"] == r["ch_ss"] and r["nb"] == r["nb_ss"], r
+        assert r["slots"] == 8 * r["nb"] + c["stash"] and r["ring"] >= 8 * r["slots"], r
+        assert r["lds"] == r["ring"] + 4 * c["ring"], r
+    # three choices above k = 1024 keep 7 blocks per CU up to k = 2048
+    # (two would leave 5 at k = 2000)
+    for r in c["freq"]:
+        if 1024 < r["k"] <= 2048:
+            assert r["ch"] == 3 and r["waves"] >= 7, r
+    assert {r["k"]: r["waves"] for r in c["freq"]}[2000] == 7

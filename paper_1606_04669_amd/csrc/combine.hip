@@ -21,13 +21,14 @@ constexpr uint8_t kAlive = 1, kCand = 2;
 
 // Storage of one COMBINE: the candidate arrays and the S2 hash ("big",
 // O(k)) live in LDS when they fit, else in a global slab per node; the
-// radix-select histogram ("small") is always in LDS.
+// radix-select histograms (two, used in turn) and the reduction words
+// ("small") are always in LDS.
 template <typename CO>
 struct CombineLds {
     uint32_t cap;   // candidate capacity (2k)
     uint32_t hsize; // S2 hash slots
     uint32_t off_cc, off_ce, off_ci, off_flag, off_hash, big_bytes;
-    uint32_t off_hist, off_misc, off_red, small_bytes;
+    uint32_t off_hist, off_misc, off_keys, off_red, small_bytes;
 
     __host__ __device__ static CombineLds make(uint32_t k) {
         CombineLds L;
@@ -42,8 +43,9 @@ struct CombineLds {
         L.off_hash = o; o = align16(o + 4 * L.hsize);
         L.big_bytes = o;
         L.off_hist = 0;
-        L.off_misc = 4 * 256;
-        L.off_red = L.off_misc + 64;
+        L.off_misc = 2 * 4 * 256;
+        L.off_keys = L.off_misc + 64;  // OR and AND of the candidates' key words
+        L.off_red = L.off_keys + 64;
         L.small_bytes = L.off_red + 8 * (kCombineThreads / kWave);
         return L;
     }
@@ -136,32 +138,84 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
     }
     __syncthreads();
 
-    // number of distinct candidates
+    // number of distinct candidates, and the OR and AND of their keys
+    // U = (~count, error, item) as six words (a digit on which all agree
+    // selects nothing)
+    uint32_t* kw = (uint32_t*)(small + L.off_keys);
     uint32_t live = 0;
-    for (uint32_t i = tid; i < nc; i += kCombineThreads) live += flag[i] & kAlive;
+    uint64_t onc = 0, anc = ~0ull, oe = 0, ae = ~0ull;
+    uint32_t oi = 0, ai = ~0u;
+    for (uint32_t i = tid; i < nc; i += kCombineThreads) {
+        if (flag[i] & kAlive) {
+            const uint64_t nc_ = (uint64_t)(CO)~cc[i], e_ = (uint64_t)ce[i];
+            const uint32_t i_ = ci[i];
+            live += 1;
+            onc |= nc_;
+            anc &= nc_;
+            oe |= e_;
+            ae &= e_;
+            oi |= i_;
+            ai &= i_;
+        }
+    }
     if (tid < 4) misc[tid] = 0;
+    if (tid < 12) kw[tid] = tid < 6 ? 0u : ~0u;  // OR words at 0..4, AND words at 6..10
     __syncthreads();
     live = wave_sum_u32(live);
-    if (lane_id() == 0) atomicAdd(&misc[0], live);
+    const uint32_t wo[5] = {(uint32_t)onc, (uint32_t)(onc >> 32), (uint32_t)oe, (uint32_t)(oe >> 32), oi};
+    const uint32_t wa[5] = {(uint32_t)anc, (uint32_t)(anc >> 32), (uint32_t)ae, (uint32_t)(ae >> 32), ai};
+    uint32_t ro[5], ra[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        ro[j] = wave_or_u32(wo[j]);
+        ra[j] = wave_and_u32(wa[j]);
+    }
+    if (lane_id() == 0) {
+        atomicAdd(&misc[0], live);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            atomicOr(&kw[j], ro[j]);
+            atomicAnd(&kw[6 + j], ra[j]);
+        }
+    }
     __syncthreads();
     const uint32_t ns = misc[0];
+    const uint64_t onc_all = ((uint64_t)kw[1] << 32) | kw[0], anc_all = ((uint64_t)kw[7] << 32) | kw[6];
+    const uint64_t oe_all = ((uint64_t)kw[3] << 32) | kw[2], ae_all = ((uint64_t)kw[9] << 32) | kw[8];
+    const uint32_t oi_all = kw[4], ai_all = kw[10];
     __syncthreads();
 
-    // Prune(k): radix select of the k-th best key when there are more than k
+    // Prune(k): radix select of the k-th best key when there are more than k.
+    // Digits on which all candidates agree are skipped; the select stops
+    // once the digit's bin holding the k-th key holds it alone; each pass
+    // filters by its digit and counts the next one in the other histogram.
     int32_t star = -1;  // index of the worst kept candidate
     if (ns > k) {
-        for (uint32_t i = tid; i < nc; i += kCombineThreads) flag[i] = (flag[i] & kAlive) ? (kAlive | kCand) : 0;
-        uint32_t rank = k - 1;
         constexpr uint32_t NB = 2 * sizeof(CO) + 4;
-        for (uint32_t p = 0; p < NB; ++p) {
-            hist[tid] = 0u;
-            __syncthreads();
-            for (uint32_t i = tid; i < nc; i += kCombineThreads)
-                if (flag[i] & kCand) atomicAdd(&hist[key_digit<CO>(cc[i], ce[i], ci[i], p)], 1u);
-            __syncthreads();
+        uint32_t vary = 0;  // digit positions where the candidates' keys differ
+        for (uint32_t p = 0; p < NB; ++p)
+            vary |= (key_digit<CO>((CO)~onc_all, (CO)oe_all, oi_all, p) !=
+                             key_digit<CO>((CO)~anc_all, (CO)ae_all, ai_all, p)
+                         ? 1u
+                         : 0u)
+                    << p;
+        // ns > k >= 1 distinct items: their keys differ somewhere
+        uint32_t p = (uint32_t)__builtin_ctz(vary | (1u << (NB - 1)));
+        uint32_t* hcur = hist;
+        uint32_t* hnext = hist + 256;
+        static_assert(kCombineThreads == 256, "one histogram bin per thread");
+        hcur[tid] = 0u;
+        hnext[tid] = 0u;
+        for (uint32_t i = tid; i < nc; i += kCombineThreads) flag[i] = (flag[i] & kAlive) ? (kAlive | kCand) : 0;
+        __syncthreads();
+        for (uint32_t i = tid; i < nc; i += kCombineThreads)
+            if (flag[i] & kCand) atomicAdd(&hcur[key_digit<CO>(cc[i], ce[i], ci[i], p)], 1u);
+        __syncthreads();
+        uint32_t rank = k - 1;
+        for (;;) {
             if (tid < kWave) {
                 // bucket holding the rank-th candidate: 4 bins per lane, then a wave scan
-                uint32_t b0 = hist[4 * tid], b1 = hist[4 * tid + 1], b2 = hist[4 * tid + 2], b3 = hist[4 * tid + 3];
+                uint32_t b0 = hcur[4 * tid], b1 = hcur[4 * tid + 1], b2 = hcur[4 * tid + 2], b3 = hcur[4 * tid + 3];
                 uint32_t s = b0 + b1 + b2 + b3, incl = s;
                 for (int off = 1; off < 64; off <<= 1) {
                     uint32_t t = (uint32_t)__shfl_up((int)incl, off);
@@ -176,14 +230,33 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
                             if (rr >= b2) { rr -= b2; ++bin; } } }
                     misc[1] = bin;
                     misc[2] = rr;
+                    misc[4] = hcur[bin];
                 }
             }
             __syncthreads();
             const uint32_t sel = misc[1];
             rank = misc[2];
-            for (uint32_t i = tid; i < nc; i += kCombineThreads)
-                if ((flag[i] & kCand) && key_digit<CO>(cc[i], ce[i], ci[i], p) != sel) flag[i] &= (uint8_t)~kCand;
+            const uint32_t alone = misc[4] == 1u;
+            vary &= ~((2u << p) - 1u);  // positions after p
+            const bool last = alone || vary == 0u;
+            const uint32_t pn = last ? p : (uint32_t)__builtin_ctz(vary);
+            hcur[tid] = 0u;  // read by the scan only: free for the pass after next
+            for (uint32_t i = tid; i < nc; i += kCombineThreads) {
+                if (flag[i] & kCand) {
+                    const CO c = cc[i], e = ce[i];
+                    const uint32_t it = ci[i];
+                    if (key_digit<CO>(c, e, it, p) != sel)
+                        flag[i] &= (uint8_t)~kCand;
+                    else if (!last)
+                        atomicAdd(&hnext[key_digit<CO>(c, e, it, pn)], 1u);
+                }
+            }
             __syncthreads();
+            if (last) break;
+            p = pn;
+            uint32_t* t = hcur;
+            hcur = hnext;
+            hnext = t;
         }
         for (uint32_t i = tid; i < nc; i += kCombineThreads)
             if (flag[i] & kCand) misc[3] = i;

@@ -16,7 +16,16 @@
 
 namespace pss {
 
+// Threads of a COMBINE workgroup: 256 where many pairs share the chip, 1024
+// (the candidates four times as fast per pair) where few pairs leave CUs idle
+// and where the candidate arrays lie in device memory.
 constexpr uint32_t kCombineThreads = 256;
+constexpr uint32_t kCombineThreadsWide = 1024;
+// Tree levels of at most this many pairs run with the wide workgroups.
+#ifndef PSS_COMBINE_WIDE_PAIRS
+#define PSS_COMBINE_WIDE_PAIRS 512
+#endif
+constexpr uint32_t kCombineWidePairs = PSS_COMBINE_WIDE_PAIRS;
 constexpr uint8_t kAlive = 1, kCand = 2;
 
 // Storage of one COMBINE: the candidate arrays and the S2 hash ("big",
@@ -46,7 +55,7 @@ struct CombineLds {
         L.off_misc = 2 * 4 * 256;
         L.off_keys = L.off_misc + 64;  // OR and AND of the candidates' key words
         L.off_red = L.off_keys + 64;
-        L.small_bytes = L.off_red + 8 * (kCombineThreads / kWave);
+        L.small_bytes = L.off_red + 8 * (kCombineThreadsWide / kWave);
         return L;
     }
 };
@@ -67,7 +76,7 @@ __device__ __forceinline__ bool better(CO ca, CO ea, uint32_t ia, CO cb, CO eb, 
     return ia < ib;
 }
 
-template <typename C1, typename C2, typename CO>
+template <uint32_t NT, typename C1, typename C2, typename CO>
 __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uint32_t n1, C1 m1_,
                              const uint32_t* i2, const C2* c2, const C2* e2, uint32_t n2, C2 m2_, uint32_t k,
                              uint32_t* io, CO* co, CO* eo, uint32_t* osize, CO* omin, unsigned char* big,
@@ -95,21 +104,21 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
     const uint32_t nc = n1 + n2;
 
     // stage S2 as candidates [n1, n1 + n2): items only in S2 get + m1
-    for (uint32_t j = tid; j < n2; j += kCombineThreads) {
+    for (uint32_t j = tid; j < n2; j += NT) {
         ci[n1 + j] = i2[j];
         cc[n1 + j] = (CO)c2[j] + m1;
         ce[n1 + j] = (CO)e2[j] + m1;
         flag[n1 + j] = kAlive;
     }
-    for (uint32_t h = tid; h < L.hsize; h += kCombineThreads) hash[h] = 0u;
+    for (uint32_t h = tid; h < L.hsize; h += NT) hash[h] = 0u;
     __syncthreads();
-    for (uint32_t j = tid; j < n2; j += kCombineThreads) {
+    for (uint32_t j = tid; j < n2; j += NT) {
         uint32_t h = hash_slot(ci[n1 + j], hbits);
         while (atomicCAS(&hash[h], 0u, j + 1u) != 0u) h = (h + 1) & hmask;
     }
     __syncthreads();
     // S1 entries: Find in S2, add both estimates (and retire S2's), or + m2
-    for (uint32_t i = tid; i < n1; i += kCombineThreads) {
+    for (uint32_t i = tid; i < n1; i += NT) {
         const uint32_t x = i1[i];
         uint32_t h = hash_slot(x, hbits);
         int32_t found = -1;
@@ -145,7 +154,7 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
     uint32_t live = 0;
     uint64_t onc = 0, anc = ~0ull, oe = 0, ae = ~0ull;
     uint32_t oi = 0, ai = ~0u;
-    for (uint32_t i = tid; i < nc; i += kCombineThreads) {
+    for (uint32_t i = tid; i < nc; i += NT) {
         if (flag[i] & kAlive) {
             const uint64_t nc_ = (uint64_t)(CO)~cc[i], e_ = (uint64_t)ce[i];
             const uint32_t i_ = ci[i];
@@ -203,12 +212,14 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
         uint32_t p = (uint32_t)__builtin_ctz(vary | (1u << (NB - 1)));
         uint32_t* hcur = hist;
         uint32_t* hnext = hist + 256;
-        static_assert(kCombineThreads == 256, "one histogram bin per thread");
-        hcur[tid] = 0u;
-        hnext[tid] = 0u;
-        for (uint32_t i = tid; i < nc; i += kCombineThreads) flag[i] = (flag[i] & kAlive) ? (kAlive | kCand) : 0;
+        static_assert(NT >= 256, "a histogram bin per thread of the first 256");
+        if (tid < 256) {
+            hcur[tid] = 0u;
+            hnext[tid] = 0u;
+        }
+        for (uint32_t i = tid; i < nc; i += NT) flag[i] = (flag[i] & kAlive) ? (kAlive | kCand) : 0;
         __syncthreads();
-        for (uint32_t i = tid; i < nc; i += kCombineThreads)
+        for (uint32_t i = tid; i < nc; i += NT)
             if (flag[i] & kCand) atomicAdd(&hcur[key_digit<CO>(cc[i], ce[i], ci[i], p)], 1u);
         __syncthreads();
         uint32_t rank = k - 1;
@@ -240,8 +251,8 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
             vary &= ~((2u << p) - 1u);  // positions after p
             const bool last = alone || vary == 0u;
             const uint32_t pn = last ? p : (uint32_t)__builtin_ctz(vary);
-            hcur[tid] = 0u;  // read by the scan only: free for the pass after next
-            for (uint32_t i = tid; i < nc; i += kCombineThreads) {
+            if (tid < 256) hcur[tid] = 0u;  // read by the scan only: free for the pass after next
+            for (uint32_t i = tid; i < nc; i += NT) {
                 if (flag[i] & kCand) {
                     const CO c = cc[i], e = ce[i];
                     const uint32_t it = ci[i];
@@ -258,7 +269,7 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
             hcur = hnext;
             hnext = t;
         }
-        for (uint32_t i = tid; i < nc; i += kCombineThreads)
+        for (uint32_t i = tid; i < nc; i += NT)
             if (flag[i] & kCand) misc[3] = i;
         __syncthreads();
         star = (int32_t)misc[3];
@@ -273,31 +284,45 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
         se = ce[star];
         si = ci[star];
     }
-    if (tid == 0) misc[0] = 0u;
-    __syncthreads();
+    // Segments of up to 32 rows of 256 candidates: each wave counts its kept
+    // candidates per row into a table, then every thread places its own from
+    // the table's running sums (the same in every thread).
+    constexpr uint32_t kWaves = NT / kWave;
+    constexpr uint32_t kRows = 32;
+    static_assert(kRows * kWaves <= 2 * 256, "the count table lies over the histograms");
+    uint32_t* rowcnt = hist;
+    const uint32_t w = tid / kWave;
     CO local_min = ~(CO)0;
-    for (uint32_t base = 0; base < nc; base += kCombineThreads) {
-        const uint32_t i = base + tid;
-        bool keep = false;
-        if (i < nc && (flag[i] & kAlive)) keep = (star < 0) || !better<CO>(sc, se, si, cc[i], ce[i], ci[i]);
-        const uint64_t bm = ballot(keep);
-        const uint32_t w = tid / kWave;
-        if (lane_id() == 0) hist[w] = popc64(bm);
-        __syncthreads();
-        uint32_t before = misc[0];
-        for (uint32_t q = 0; q < w; ++q) before += hist[q];
-        if (keep) {
-            const uint32_t o = before + mbcnt(bm);
-            io[o] = ci[i];
-            co[o] = cc[i];
-            eo[o] = ce[i];
-            local_min = cc[i] < local_min ? cc[i] : local_min;
+    uint32_t kept = 0;
+    for (uint32_t seg = 0; seg < nc; seg += kRows * NT) {
+        const uint32_t rows = min(kRows, (nc - seg + NT - 1) / NT);
+        uint32_t keepbits = 0;
+        for (uint32_t q = 0; q < rows; ++q) {
+            const uint32_t i = seg + q * NT + tid;
+            bool keep = false;
+            if (i < nc && (flag[i] & kAlive)) keep = (star < 0) || !better<CO>(sc, se, si, cc[i], ce[i], ci[i]);
+            const uint64_t bm = ballot(keep);
+            if (lane_id() == 0) rowcnt[kWaves * q + w] = popc64(bm);
+            keepbits |= (keep ? 1u : 0u) << q;
         }
         __syncthreads();
-        if (tid == 0) misc[0] += hist[0] + hist[1] + hist[2] + hist[3];
-        __syncthreads();
+        for (uint32_t q = 0; q < rows; ++q) {
+            const bool keep = (keepbits >> q) & 1u;
+            const uint64_t bm = ballot(keep);
+            uint32_t before = kept;
+            for (uint32_t v = 0; v < w; ++v) before += rowcnt[kWaves * q + v];
+            if (keep) {
+                const uint32_t i = seg + q * NT + tid;
+                const uint32_t o = before + mbcnt(bm);
+                io[o] = ci[i];
+                co[o] = cc[i];
+                eo[o] = ce[i];
+                local_min = cc[i] < local_min ? cc[i] : local_min;
+            }
+            for (uint32_t v = 0; v < kWaves; ++v) kept += rowcnt[kWaves * q + v];
+        }
+        __syncthreads();  // the table is read before the next segment rewrites it
     }
-    const uint32_t kept = misc[0];
     // minimum of the result: 0 unless all k counters are used
     CO wmin = wave_min_u64((uint64_t)local_min);
     uint64_t* red = (uint64_t*)(small + L.off_red);
@@ -305,7 +330,7 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
     __syncthreads();
     if (tid == 0) {
         uint64_t mn = red[0];
-        for (uint32_t q = 1; q < kCombineThreads / kWave; ++q) mn = red[q] < mn ? red[q] : mn;
+        for (uint32_t q = 1; q < NT / kWave; ++q) mn = red[q] < mn ? red[q] : mn;
         *osize = kept;
         *omin = (kept == k) ? (CO)mn : (CO)0;
     }
@@ -314,8 +339,8 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
 // One workgroup per pair of the level, or (global storage) a bounded grid
 // whose workgroups each reuse one scratch slab for pairs blockIdx, blockIdx +
 // gridDim, ...
-template <bool G>
-__global__ __launch_bounds__(kCombineThreads) void combine_level_kernel(BlockSummaries v, uint32_t k, uint32_t count,
+template <bool G, uint32_t NT>
+__global__ __launch_bounds__(NT) void combine_level_kernel(BlockSummaries v, uint32_t k, uint32_t count,
                                                                         uint32_t step, uint32_t pairs,
                                                                         unsigned char* scratch, uint32_t big_bytes) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -324,7 +349,7 @@ __global__ __launch_bounds__(kCombineThreads) void combine_level_kernel(BlockSum
         const uint64_t a = 2ull * step * j;
         const uint64_t b = a + step;
         __syncthreads();  // the previous pair is done with the slab
-        combine_node<uint32_t, uint32_t, uint32_t>(v.item + a * k, v.cnt + a * k, v.err + a * k, v.size[a], v.min[a],
+        combine_node<NT, uint32_t, uint32_t, uint32_t>(v.item + a * k, v.cnt + a * k, v.err + a * k, v.size[a], v.min[a],
                                                    v.item + b * k, v.cnt + b * k, v.err + b * k, v.size[b], v.min[b],
                                                    k, v.item + a * k, v.cnt + a * k, v.err + a * k, &v.size[a],
                                                    &v.min[a], big, smem);
@@ -335,7 +360,7 @@ __global__ __launch_bounds__(kCombineThreads) void combine_level_kernel(BlockSum
 // block's failure mark leaves d (entries, header and N) as it was and sets
 // d's fault word, which the next report hands to the host.
 template <bool G>
-__global__ __launch_bounds__(kCombineThreads) void fold_kernel(WideSummary d, BlockSummaries s, uint32_t k,
+__global__ __launch_bounds__(kCombineThreadsWide) void fold_kernel(WideSummary d, BlockSummaries s, uint32_t k,
                                                                uint64_t n, unsigned char* scratch) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* big = G ? scratch : smem + CombineLds<uint64_t>::make(k).small_bytes;
@@ -344,13 +369,14 @@ __global__ __launch_bounds__(kCombineThreads) void fold_kernel(WideSummary d, Bl
         if (threadIdx.x == 0) *d.fault = 1u;
         return;
     }
-    combine_node<uint64_t, uint32_t, uint64_t>(d.item, d.cnt, d.err, n1, d.min[0], s.item, s.cnt, s.err, n2, s.min[0],
-                                               k, d.item, d.cnt, d.err, d.size, d.min, big, smem);
+    combine_node<kCombineThreadsWide, uint64_t, uint32_t, uint64_t>(d.item, d.cnt, d.err, n1, d.min[0], s.item, s.cnt,
+                                                                    s.err, n2, s.min[0], k, d.item, d.cnt, d.err,
+                                                                    d.size, d.min, big, smem);
     if (threadIdx.x == 0) *d.total += n;
 }
 
 template <bool G>
-__global__ __launch_bounds__(kCombineThreads) void merge_kernel(WideSummary d, WideSummary s, uint32_t k,
+__global__ __launch_bounds__(kCombineThreadsWide) void merge_kernel(WideSummary d, WideSummary s, uint32_t k,
                                                                 unsigned char* scratch) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* big = G ? scratch : smem + CombineLds<uint64_t>::make(k).small_bytes;
@@ -360,8 +386,9 @@ __global__ __launch_bounds__(kCombineThreads) void merge_kernel(WideSummary d, W
         return;
     }
     const uint64_t ns = *s.total;
-    combine_node<uint64_t, uint64_t, uint64_t>(d.item, d.cnt, d.err, n1, d.min[0], s.item, s.cnt, s.err, n2, s.min[0],
-                                               k, d.item, d.cnt, d.err, d.size, d.min, big, smem);
+    combine_node<kCombineThreadsWide, uint64_t, uint64_t, uint64_t>(d.item, d.cnt, d.err, n1, d.min[0], s.item, s.cnt,
+                                                                    s.err, n2, s.min[0], k, d.item, d.cnt, d.err,
+                                                                    d.size, d.min, big, smem);
     if (threadIdx.x == 0) *d.total += ns;
 }
 
@@ -374,7 +401,7 @@ __global__ __launch_bounds__(kCombineThreads) void batch_combine_kernel(const Ba
     for (uint32_t j = blockIdx.x; j < count; j += gridDim.x) {
         const BatchNode nd = nodes[j];
         __syncthreads();  // the previous node is done with LDS
-        combine_node<uint32_t, uint32_t, uint32_t>(v.item + nd.a_off, v.cnt + nd.a_off, v.err + nd.a_off, v.size[nd.a],
+        combine_node<kCombineThreads, uint32_t, uint32_t, uint32_t>(v.item + nd.a_off, v.cnt + nd.a_off, v.err + nd.a_off, v.size[nd.a],
                                                    v.min[nd.a], v.item + nd.b_off, v.cnt + nd.b_off,
                                                    v.err + nd.b_off, v.size[nd.b], v.min[nd.b], nd.k,
                                                    v.item + nd.a_off, v.cnt + nd.a_off, v.err + nd.a_off,
@@ -409,7 +436,7 @@ __global__ __launch_bounds__(kCombineThreads) void serve_fold_kernel(const Serve
             if (threadIdx.x == 0) *failed = 1u;
             continue;
         }
-        combine_node<uint64_t, uint32_t, uint64_t>(pool.item + d.s_off, pool.cnt + d.s_off, pool.err + d.s_off, n1,
+        combine_node<kCombineThreads, uint64_t, uint32_t, uint64_t>(pool.item + d.s_off, pool.cnt + d.s_off, pool.err + d.s_off, n1,
                                                    pool.min[d.sid], v.item + d.root_off, v.cnt + d.root_off,
                                                    v.err + d.root_off, n2, v.min[d.root], d.k, pool.item + d.s_off,
                                                    pool.cnt + d.s_off, pool.err + d.s_off, &pool.size[d.sid],
@@ -444,17 +471,29 @@ hipError_t launch_combine_level(const BlockSummaries& v, uint32_t k, uint32_t co
     // pairs (a, a + step) with a = 2 step j and a + step < count
     const uint32_t pairs = (uint32_t)(((uint64_t)count - step + 2ull * step - 1) / (2ull * step));
     const CombineLds<uint32_t> L = CombineLds<uint32_t>::make(k);
+    // levels of few pairs, and every level with the arrays in device memory
+    // (bounded grid, large k), take the wide workgroups
+    const bool wide = !in_lds || pairs <= kCombineWidePairs;
     if (in_lds) {
         const uint32_t lds = L.big_bytes + L.small_bytes;
-        hipFuncSetAttribute((const void*)combine_level_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
-        hipLaunchKernelGGL(combine_level_kernel<false>, dim3(pairs), dim3(kCombineThreads), lds, stream, v, k, count,
-                           step, pairs, (unsigned char*)nullptr, 0u);
+        auto launch = [&](auto kern, uint32_t nt) {
+            hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(kern, dim3(pairs), dim3(nt), lds, stream, v, k, count, step, pairs,
+                               (unsigned char*)nullptr, 0u);
+        };
+        if (wide)
+            launch(combine_level_kernel<false, kCombineThreadsWide>, kCombineThreadsWide);
+        else
+            launch(combine_level_kernel<false, kCombineThreads>, kCombineThreads);
     } else {
         if (!scratch || slabs == 0) return hipErrorInvalidValue;
         const uint32_t grid = pairs < slabs ? pairs : slabs;
-        hipLaunchKernelGGL(combine_level_kernel<true>, dim3(grid), dim3(kCombineThreads), L.small_bytes, stream, v, k,
-                           count, step, pairs, scratch, L.big_bytes);
+        if (wide)
+            hipLaunchKernelGGL((combine_level_kernel<true, kCombineThreadsWide>), dim3(grid), dim3(kCombineThreadsWide),
+                               L.small_bytes, stream, v, k, count, step, pairs, scratch, L.big_bytes);
+        else
+            hipLaunchKernelGGL((combine_level_kernel<true, kCombineThreads>), dim3(grid), dim3(kCombineThreads),
+                               L.small_bytes, stream, v, k, count, step, pairs, scratch, L.big_bytes);
     }
     return hipGetLastError();
 }
@@ -467,11 +506,11 @@ hipError_t launch_fold(const WideSummary& dst, const BlockSummaries& src, uint32
     if (in_lds) {
         const uint32_t lds = L.big_bytes + L.small_bytes;
         hipFuncSetAttribute((const void*)fold_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(fold_kernel<false>, dim3(1), dim3(kCombineThreads), lds, stream, dst, src, k, n,
+        hipLaunchKernelGGL(fold_kernel<false>, dim3(1), dim3(kCombineThreadsWide), lds, stream, dst, src, k, n,
                            (unsigned char*)nullptr);
     } else {
         if (!scratch) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(fold_kernel<true>, dim3(1), dim3(kCombineThreads), L.small_bytes, stream, dst, src, k, n,
+        hipLaunchKernelGGL(fold_kernel<true>, dim3(1), dim3(kCombineThreadsWide), L.small_bytes, stream, dst, src, k, n,
                            scratch);
     }
     return hipGetLastError();
@@ -485,11 +524,11 @@ hipError_t launch_merge(const WideSummary& dst, const WideSummary& src, uint32_t
     if (in_lds) {
         const uint32_t lds = L.big_bytes + L.small_bytes;
         hipFuncSetAttribute((const void*)merge_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(merge_kernel<false>, dim3(1), dim3(kCombineThreads), lds, stream, dst, src, k,
+        hipLaunchKernelGGL(merge_kernel<false>, dim3(1), dim3(kCombineThreadsWide), lds, stream, dst, src, k,
                            (unsigned char*)nullptr);
     } else {
         if (!scratch) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(merge_kernel<true>, dim3(1), dim3(kCombineThreads), L.small_bytes, stream, dst, src, k,
+        hipLaunchKernelGGL(merge_kernel<true>, dim3(1), dim3(kCombineThreadsWide), L.small_bytes, stream, dst, src, k,
                            scratch);
     }
     return hipGetLastError();

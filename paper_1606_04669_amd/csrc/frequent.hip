@@ -353,10 +353,14 @@ __global__ __launch_bounds__(64) void frequent_block_kernel(const uint32_t* __re
 
 // ---------------------------------------------------------------------------
 // Merge: S_C = union with added counts; beyond k - 1 items subtract the
-// k-th largest count c; D = D1 + D2 + c.  One 256-thread workgroup per pair.
+// k-th largest count c; D = D1 + D2 + c.  One workgroup per pair.
 // ---------------------------------------------------------------------------
 
+// 256 threads per pair where many pairs share the chip, 1024 on levels of at
+// most 512 pairs, where few pairs leave CUs idle.
 constexpr uint32_t kMergeThreads = 256;
+constexpr uint32_t kMergeThreadsWide = 1024;
+constexpr uint32_t kMergeWidePairs = 512;
 
 struct FqMergeLds {
     uint32_t cap, hsize;
@@ -371,13 +375,14 @@ struct FqMergeLds {
         L.off_ci = o;   o = align16(o + 4 * L.cap);
         L.off_flag = o; o = align16(o + L.cap);
         L.off_hash = o; o = align16(o + 4 * L.hsize);
-        L.off_hist = o; o = align16(o + 4 * 256);
+        L.off_hist = o; o = align16(o + 2 * 4 * 256);  // two select histograms, used in turn
         L.off_misc = o; o = align16(o + 64);
         L.bytes = o;
         return L;
     }
 };
 
+template <uint32_t NT>
 __device__ void frequent_merge_node(const uint32_t* i1, const uint32_t* c1, uint32_t n1, uint32_t d1,
                                     const uint32_t* i2, const uint32_t* c2, uint32_t n2, uint32_t d2, uint32_t k,
                                     uint32_t* io, uint32_t* co, uint32_t* eo, uint32_t* osize, uint32_t* odec) {
@@ -400,19 +405,19 @@ __device__ void frequent_merge_node(const uint32_t* i1, const uint32_t* c1, uint
         return;
     }
     const uint32_t nc = n1 + n2;
-    for (uint32_t j = tid; j < n2; j += kMergeThreads) {
+    for (uint32_t j = tid; j < n2; j += NT) {
         ci[n1 + j] = i2[j];
         cc[n1 + j] = c2[j];
         flag[n1 + j] = 1;
     }
-    for (uint32_t h = tid; h < L.hsize; h += kMergeThreads) hash[h] = 0u;
+    for (uint32_t h = tid; h < L.hsize; h += NT) hash[h] = 0u;
     __syncthreads();
-    for (uint32_t j = tid; j < n2; j += kMergeThreads) {
+    for (uint32_t j = tid; j < n2; j += NT) {
         uint32_t h = hash_slot(ci[n1 + j], hbits);
         while (atomicCAS(&hash[h], 0u, j + 1u) != 0u) h = (h + 1) & hmask;
     }
     __syncthreads();
-    for (uint32_t i = tid; i < n1; i += kMergeThreads) {
+    for (uint32_t i = tid; i < n1; i += NT) {
         const uint32_t x = i1[i];
         uint32_t h = hash_slot(x, hbits);
         uint32_t c = c1[i];
@@ -430,93 +435,156 @@ __device__ void frequent_merge_node(const uint32_t* i1, const uint32_t* c1, uint
         cc[i] = c;
         flag[i] = 1;
     }
-    if (tid < 4) misc[tid] = 0;
+    if (tid < 8) misc[tid] = tid == 5 ? ~0u : 0u;
     __syncthreads();
-    uint32_t live = 0;
-    for (uint32_t i = tid; i < nc; i += kMergeThreads) live += flag[i];
+    // distinct candidates, and the OR and AND of their inverted counts (a
+    // byte on which all agree selects nothing)
+    uint32_t live = 0, ov = 0u, av = ~0u;
+    for (uint32_t i = tid; i < nc; i += NT) {
+        if (flag[i]) {
+            live += 1;
+            ov |= ~cc[i];
+            av &= ~cc[i];
+        }
+    }
     live = wave_sum_u32(live);
-    if (lane_id() == 0) atomicAdd(&misc[0], live);
+    ov = wave_or_u32(ov);
+    av = wave_and_u32(av);
+    if (lane_id() == 0) {
+        atomicAdd(&misc[0], live);
+        atomicOr(&misc[4], ov);
+        atomicAnd(&misc[5], av);
+    }
     __syncthreads();
     const uint32_t ns = misc[0];
+    const uint32_t differ = misc[4] ^ misc[5], common = ~misc[5];
     __syncthreads();
 
     // the k-th largest count (rank K1 from the top), by an MSD radix select
-    // over the four bytes of ~count; candidates still in the running carry
-    // flag bit 2
+    // over the bytes of ~count where the candidates differ; candidates still
+    // in the running carry flag bit 2.  Each pass filters by its byte and
+    // counts the next one in the other histogram; the select stops once the
+    // bin holding the k-th count holds nothing else.
     uint32_t cut = 0;
     if (ns > K1) {
-        for (uint32_t i = tid; i < nc; i += kMergeThreads) flag[i] = flag[i] ? 3 : 0;
-        uint32_t rank = K1;
-        for (uint32_t p = 0; p < 4; ++p) {
-            const uint32_t sh = 8u * (3u - p);
-            hist[tid] = 0u;
-            __syncthreads();
-            for (uint32_t i = tid; i < nc; i += kMergeThreads)
-                if (flag[i] & 2) atomicAdd(&hist[((~cc[i]) >> sh) & 255u], 1u);
-            __syncthreads();
-            if (tid < kWave) {
-                const uint32_t b0 = hist[4 * tid], b1 = hist[4 * tid + 1], b2 = hist[4 * tid + 2],
-                               b3 = hist[4 * tid + 3];
-                const uint32_t s = b0 + b1 + b2 + b3;
-                uint32_t incl = s;
-                for (int off = 1; off < 64; off <<= 1) {
-                    const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
-                    if ((int)tid >= off) incl += t;
-                }
-                const uint32_t excl = incl - s;
-                if (excl <= rank && rank < incl) {
-                    uint32_t rr = rank - excl, bin = 4 * tid;
-                    if (rr >= b0) { rr -= b0; ++bin;
-                        if (rr >= b1) { rr -= b1; ++bin;
-                            if (rr >= b2) { rr -= b2; ++bin; } } }
-                    misc[1] = bin;
-                    misc[2] = rr;
-                }
+        uint32_t vary = 0;
+        for (uint32_t p = 0; p < 4; ++p) vary |= ((differ >> (8u * (3u - p))) & 255u ? 1u : 0u) << p;
+        if (vary == 0u) {
+            cut = common;  // every candidate has this count
+        } else {
+            uint32_t p = (uint32_t)__builtin_ctz(vary);
+            uint32_t* hcur = hist;
+            uint32_t* hnext = hist + 256;
+            static_assert(NT >= 256, "a histogram bin per thread of the first 256");
+            if (tid < 256) {
+                hcur[tid] = 0u;
+                hnext[tid] = 0u;
             }
+            for (uint32_t i = tid; i < nc; i += NT) flag[i] = flag[i] ? 3 : 0;
             __syncthreads();
-            const uint32_t sel = misc[1];
-            rank = misc[2];
-            for (uint32_t i = tid; i < nc; i += kMergeThreads)
-                if ((flag[i] & 2) && (((~cc[i]) >> sh) & 255u) != sel) flag[i] &= 1;
+            for (uint32_t i = tid; i < nc; i += NT)
+                if (flag[i] & 2) atomicAdd(&hcur[((~cc[i]) >> (8u * (3u - p))) & 255u], 1u);
             __syncthreads();
+            uint32_t rank = K1;
+            for (;;) {
+                if (tid < kWave) {
+                    const uint32_t b0 = hcur[4 * tid], b1 = hcur[4 * tid + 1], b2 = hcur[4 * tid + 2],
+                                   b3 = hcur[4 * tid + 3];
+                    const uint32_t s = b0 + b1 + b2 + b3;
+                    uint32_t incl = s;
+                    for (int off = 1; off < 64; off <<= 1) {
+                        const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
+                        if ((int)tid >= off) incl += t;
+                    }
+                    const uint32_t excl = incl - s;
+                    if (excl <= rank && rank < incl) {
+                        uint32_t rr = rank - excl, bin = 4 * tid;
+                        if (rr >= b0) { rr -= b0; ++bin;
+                            if (rr >= b1) { rr -= b1; ++bin;
+                                if (rr >= b2) { rr -= b2; ++bin; } } }
+                        misc[1] = bin;
+                        misc[2] = rr;
+                        misc[6] = hcur[bin];
+                    }
+                }
+                __syncthreads();
+                const uint32_t sel = misc[1];
+                rank = misc[2];
+                const bool alone = misc[6] == 1u;
+                vary &= ~((2u << p) - 1u);  // bytes after p
+                const bool last = alone || vary == 0u;
+                const uint32_t pn = last ? p : (uint32_t)__builtin_ctz(vary);
+                if (tid < 256) hcur[tid] = 0u;  // read by the scan only: free for the pass after next
+                for (uint32_t i = tid; i < nc; i += NT) {
+                    if (flag[i] & 2) {
+                        const uint32_t v = ~cc[i];
+                        if (((v >> (8u * (3u - p))) & 255u) != sel)
+                            flag[i] &= 1;
+                        else if (!last)
+                            atomicAdd(&hnext[(v >> (8u * (3u - pn))) & 255u], 1u);
+                    }
+                }
+                __syncthreads();
+                if (last) break;
+                p = pn;
+                uint32_t* t = hcur;
+                hcur = hnext;
+                hnext = t;
+            }
+            for (uint32_t i = tid; i < nc; i += NT)
+                if (flag[i] & 2) misc[3] = cc[i];  // every candidate left has that count
+            __syncthreads();
+            cut = misc[3];
         }
-        for (uint32_t i = tid; i < nc; i += kMergeThreads)
-            if (flag[i] & 2) misc[3] = cc[i];  // every candidate left has that count
-        __syncthreads();
-        cut = misc[3];
     }
-    if (tid == 0) misc[0] = 0u;
-    __syncthreads();
-    // keep the counts above the cut, lowered by it, in candidate order
-    for (uint32_t base = 0; base < nc; base += kMergeThreads) {
-        const uint32_t i = base + tid;
-        const bool keep = i < nc && (flag[i] & 1) && cc[i] > cut;
-        const uint64_t bm = ballot(keep);
-        const uint32_t w = tid / kWave;
-        if (lane_id() == 0) hist[w] = popc64(bm);
-        __syncthreads();
-        uint32_t before = misc[0];
-        for (uint32_t q = 0; q < w; ++q) before += hist[q];
-        if (keep) {
-            const uint32_t o = before + mbcnt(bm);
-            io[o] = ci[i];
-            co[o] = cc[i] - cut;
-            eo[o] = 0u;
+    // keep the counts above the cut, lowered by it, in candidate order: rows
+    // of NT candidates, up to 32 rows per segment, each wave's kept count per
+    // row in a table over the histograms
+    constexpr uint32_t kWaves = NT / kWave;
+    constexpr uint32_t kRows = 32;
+    static_assert(kRows * kWaves <= 2 * 256, "the count table lies over the histograms");
+    uint32_t* rowcnt = hist;
+    const uint32_t w = tid / kWave;
+    uint32_t kept = 0;
+    __syncthreads();  // the select's last reads of the histograms are done
+    for (uint32_t seg = 0; seg < nc; seg += kRows * NT) {
+        const uint32_t rows = min(kRows, (nc - seg + NT - 1) / NT);
+        uint32_t keepbits = 0;
+        for (uint32_t q = 0; q < rows; ++q) {
+            const uint32_t i = seg + q * NT + tid;
+            const bool keep = i < nc && (flag[i] & 1) && cc[i] > cut;
+            const uint64_t bm = ballot(keep);
+            if (lane_id() == 0) rowcnt[kWaves * q + w] = popc64(bm);
+            keepbits |= (keep ? 1u : 0u) << q;
         }
         __syncthreads();
-        if (tid == 0) misc[0] += hist[0] + hist[1] + hist[2] + hist[3];
-        __syncthreads();
+        for (uint32_t q = 0; q < rows; ++q) {
+            const bool keep = (keepbits >> q) & 1u;
+            const uint64_t bm = ballot(keep);
+            uint32_t before = kept;
+            for (uint32_t u = 0; u < w; ++u) before += rowcnt[kWaves * q + u];
+            if (keep) {
+                const uint32_t i = seg + q * NT + tid;
+                const uint32_t o = before + mbcnt(bm);
+                io[o] = ci[i];
+                co[o] = cc[i] - cut;
+                eo[o] = 0u;
+            }
+            for (uint32_t u = 0; u < kWaves; ++u) kept += rowcnt[kWaves * q + u];
+        }
+        __syncthreads();  // the table is read before the next segment rewrites it
     }
     if (tid == 0) {
-        *osize = misc[0];
+        *osize = kept;
         *odec = d1 + d2 + cut;
     }
 }
 
-__global__ __launch_bounds__(kMergeThreads) void frequent_level_kernel(BlockSummaries v, uint32_t k, uint32_t step) {
+template <uint32_t NT>
+__global__ __launch_bounds__(NT) void frequent_level_kernel(BlockSummaries v, uint32_t k, uint32_t step) {
     const uint64_t a = 2ull * step * blockIdx.x;
     const uint64_t b = a + step;
-    frequent_merge_node(v.item + a * k, v.cnt + a * k, v.size[a], v.min[a], v.item + b * k, v.cnt + b * k, v.size[b],
+    frequent_merge_node<NT>(v.item + a * k, v.cnt + a * k, v.size[a], v.min[a], v.item + b * k, v.cnt + b * k, v.size[b],
                         v.min[b], k, v.item + a * k, v.cnt + a * k, v.err + a * k, &v.size[a], &v.min[a]);
 }
 
@@ -547,8 +615,14 @@ hipError_t launch_frequent_level(const BlockSummaries& v, uint32_t k, uint32_t c
     if (step >= count) return hipSuccess;
     const uint32_t pairs = (uint32_t)(((uint64_t)count - step + 2ull * step - 1) / (2ull * step));
     const uint32_t lds = FqMergeLds::make(k).bytes;
-    hipFuncSetAttribute((const void*)frequent_level_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(frequent_level_kernel, dim3(pairs), dim3(kMergeThreads), lds, stream, v, k, step);
+    auto launch = [&](auto kern, uint32_t nt) {
+        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, dim3(pairs), dim3(nt), lds, stream, v, k, step);
+    };
+    if (pairs <= kMergeWidePairs)
+        launch(frequent_level_kernel<kMergeThreadsWide>, kMergeThreadsWide);
+    else
+        launch(frequent_level_kernel<kMergeThreads>, kMergeThreads);
     return hipGetLastError();
 }
 

@@ -558,8 +558,8 @@ def main():
     ap.add_argument("--chunks", default="tuned", choices=["tuned", "planner"],
                     help="chunk count per case: the library's autotuner (pss_tune_chunks) or its planner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-log2", type=int, default=24)
-    ap.add_argument("--cpu-threads-sample-log2", type=int, default=26)
+    ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--cpu-threads-sample-log2", type=int, default=27)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served leg")
     ap.add_argument("--no-highk", action="store_true", help="skip the high-k leg")

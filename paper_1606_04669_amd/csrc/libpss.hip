@@ -36,12 +36,11 @@ thread_local int t_last_device_error = 0;
 
 namespace {
 // Blocks for n items and k counters when per_cu block waves fit a CU at once:
-// enough resident waves to cover every CU a few times over, while keeping
-// blocks long next to k (the reduction tree moves ~C*k entries).
-uint64_t plan_for_residency(int cu_count, uint64_t per_cu, uint64_t n, uint32_t k) {
+// `rounds` times the resident waves of the chip, while keeping blocks long
+// next to k (the reduction tree moves ~C*k entries).
+uint64_t plan_for_residency(int cu_count, uint64_t per_cu, uint64_t n, uint32_t k, uint64_t rounds) {
     per_cu = std::min<uint64_t>(std::max<uint64_t>(per_cu, 1), 32);  // 32 waves per CU at most
-    // many resident waves (small k): twice the rounds, the tree stays cheap
-    const uint64_t want = (uint64_t)std::max(cu_count, 1) * per_cu * (per_cu >= 8 ? 2 * kPlanRounds : kPlanRounds);
+    const uint64_t want = (uint64_t)std::max(cu_count, 1) * per_cu * rounds;
     uint64_t cap_len = n / (16ull * k);
     if (cap_len < 1) cap_len = 1;
     return std::min(want, cap_len);
@@ -52,7 +51,13 @@ uint32_t plan_chunks(int cu_count, size_t lds_per_cu, size_t lds_max, uint64_t n
     if (n == 0 || k < 2) return 1;
     if (k > kMaxK) k = kMaxK;
     const ChunkLayout L = chunk_layout(k, lds_max);
-    uint64_t c = plan_for_residency(cu_count, lds_waves(lds_per_cu, L.lds_bytes), n, k);
+    const uint64_t per_cu = lds_waves(lds_per_cu, L.lds_bytes);
+    // many resident waves (small k): twice the rounds, the tree stays cheap.
+    // The LDS classes with few resident waves (k > 1024) run one round: their
+    // blocks are alike in length and finish together, and their tree is the
+    // costly one.
+    const uint64_t rounds = per_cu >= 8 ? 2 * kPlanRounds : L.global_state ? kPlanRounds : 1;
+    uint64_t c = plan_for_residency(cu_count, per_cu, n, k, rounds);
     if (L.global_state) c = std::min<uint64_t>(c, kStateBudget / (L.state_bytes + 4ull * L.err_stride));
     c = std::min<uint64_t>(c, kMaxChunks);
     return (uint32_t)std::max<uint64_t>(c, 1);
@@ -61,7 +66,10 @@ uint32_t plan_chunks(int cu_count, size_t lds_per_cu, size_t lds_max, uint64_t n
 uint32_t plan_frequent_chunks(int cu_count, size_t lds_per_cu, uint64_t n, uint32_t k) {
     if (n == 0 || k < 2) return 1;
     if (k > kMaxK) k = kMaxK;
-    const uint64_t c = plan_for_residency(cu_count, lds_waves(lds_per_cu, FreqLayout::make(k).lds_bytes), n, k);
+    const uint64_t per_cu = lds_waves(lds_per_cu, FreqLayout::make(k).lds_bytes);
+    // the Frequent block's decrement passes make its block lengths uneven:
+    // several rounds even them out
+    const uint64_t c = plan_for_residency(cu_count, per_cu, n, k, per_cu >= 8 ? 2 * kPlanRounds : kPlanRounds);
     return (uint32_t)std::max<uint64_t>(std::min<uint64_t>(c, kMaxChunks), 1);
 }
 }  // namespace pss

@@ -43,10 +43,10 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, n_log2: int, k: int):
+def measured_traffic(workload: str, n_log2: int, k: int, split: bool = False):
     """HBM bytes per launch of the block kernel's instance for k, from the
-    committed counter runs, or None when they were taken on another kernel
-    source or workload."""
+    committed counter runs (split: [read, write]), or None when they were
+    taken on another kernel source or workload."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -56,6 +56,8 @@ def measured_traffic(workload: str, n_log2: int, k: int):
         return None
     if t.get("workload") != workload or t.get("n_log2") != n_log2:
         return None
+    if split:
+        return t.get("read_write_bytes_per_launch_by_k", {}).get(str(k))
     return t.get("bytes_per_launch_by_k", {}).get(str(k))
 
 
@@ -660,6 +662,7 @@ def main():
             "unit": "GB/s",
             "frac": round(dom["achieved"] / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.workload, n_log2, dom["k"]),
+            "traffic_read_write": measured_traffic(args.workload, n_log2, dom["k"], split=True),
             "avg_launch_ms": dom_launch_ms,
             "launches": dom["launches"],
             "measured_read_gbs": round(read_gbs, 1),

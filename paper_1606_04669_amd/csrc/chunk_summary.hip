@@ -83,11 +83,12 @@ struct LdsIds {
     __device__ __forceinline__ uint32_t operator()(uint32_t s) const { return words[2 * s]; }
 };
 
-// Count of a slot's entry (the high word), or ~0 when the slot holds no
-// counter (empty, or claimed during a window).
-__device__ __forceinline__ uint32_t slot_count(const uint32_t* words, uint32_t s) {
+// Count of a slot's entry (the high word under cmask, which drops a packed
+// error), or ~0 when the slot holds no counter (empty, or claimed during a
+// window).
+__device__ __forceinline__ uint32_t slot_count(const uint32_t* words, uint32_t s, uint32_t cmask) {
     const uint32_t c = words[2 * s + 1];
-    return live_tag(c) ? c : 0xFFFFFFFFu;
+    return live_tag(c) ? (c & cmask) : 0xFFFFFFFFu;
 }
 
 // A count word that other lanes have just changed with atomics: from LDS
@@ -579,7 +580,7 @@ __device__ __forceinline__ uint64_t level_lds_body(uint32_t sbo, const ChunkLayo
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t s = b + j * kWave + lane;
-            const uint32_t c = slot_count(words, s < S ? s : 0u);  // clamped: no branch around the load
+            const uint32_t c = slot_count(words, s < S ? s : 0u, L.count_mask);  // clamped: no branch around the load
             cv[j] = s < S ? c : 0xFFFFFFFFu;
         }
 #pragma unroll
@@ -599,7 +600,7 @@ __device__ __forceinline__ uint64_t level_lds_body(uint32_t sbo, const ChunkLayo
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const uint32_t s = b + j * kWave + lane;
-                const uint32_t c = slot_count(words, s < S ? s : 0u);  // clamped: no branch around the load
+                const uint32_t c = slot_count(words, s < S ? s : 0u, L.count_mask);  // clamped: no branch around the load
             cv[j] = s < S ? c : 0xFFFFFFFFu;
             }
 #pragma unroll
@@ -649,7 +650,7 @@ __device__ __forceinline__ uint64_t build_level_global(unsigned char* sb, unsign
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             const uint32_t s = b + j * kWave + lane;
-            const uint32_t c = slot_count(words, s < S ? s : 0u);  // clamped: no branch around the load
+            const uint32_t c = slot_count(words, s < S ? s : 0u, L.count_mask);  // clamped: no branch around the load
             cv[j] = s < S ? c : 0xFFFFFFFFu;
         }
 #pragma unroll
@@ -669,7 +670,7 @@ __device__ __forceinline__ uint64_t build_level_global(unsigned char* sb, unsign
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 const uint32_t s = b + j * kWave + lane;
-                const uint32_t c = slot_count(words, s < S ? s : 0u);  // clamped: no branch around the load
+                const uint32_t c = slot_count(words, s < S ? s : 0u, L.count_mask);  // clamped: no branch around the load
             cv[j] = s < S ? c : 0xFFFFFFFFu;
             }
 #pragma unroll
@@ -699,12 +700,13 @@ __device__ __forceinline__ uint64_t build_level_global(unsigned char* sb, unsign
 // G: the state at sb lives in global memory with 32-bit indices (k whose
 // state does not fit LDS), else sb is in LDS.  lds holds the input ring and
 // the per-window arrays; errs is the block's error scratch (one error of
-// L.err_bytes bytes per slot).  Writes entries [0, size) to o_item/o_cnt/o_err and the header to
+// L.err_bytes bytes per slot; PK: none, each error rides in its counter's
+// count word above kCountBits).  Writes entries [0, size) to o_item/o_cnt/o_err and the header to
 // *o_size, *o_min.  Returns kOverflow, with nothing written, when a new
 // item found no free slot under the hash functions hk (the caller runs the
 // block again with other ones); else kDone.
 constexpr uint32_t kDone = 0, kOverflow = 1;
-template <int P, bool G, bool EB = false>
+template <int P, bool G, bool PK = false>
 __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__ items, uint64_t n, uint64_t begin,
                                                     uint64_t end, const ChunkLayout& L, int vec_ok, unsigned char* sb,
                                                     unsigned char* lds, uint32_t* __restrict__ errs,
@@ -725,18 +727,23 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
     const SlotIds ids{table};
     uint32_t* ring = (uint32_t*)(lds + L.off_ring);
     const uint4* stash4 = tbl4 + T / 2;
-    // the block's error scratch at the layout's width (EB: 1 byte, known at
-    // compile time, so the window loop has no width switch)
-    const uint32_t ew = EB ? 1u : L.err_bytes;
+    // the block's error scratch at the layout's width; PK (known at compile
+    // time): none, a counter's count word holds its error above the count,
+    // and cmask selects the count
+    constexpr uint32_t cmask = PK ? kCountMask : 0xFFFFFFFFu;
+    const uint32_t ew = L.err_bytes;
     auto err_put = [&](uint32_t s, uint32_t e) {
-        if (ew == 1)
-            ((uint8_t*)errs)[s] = (uint8_t)e;
-        else if (ew == 2)
-            ((uint16_t*)errs)[s] = (uint16_t)e;
-        else
-            errs[s] = e;
+        if constexpr (!PK) {
+            if (ew == 1)
+                ((uint8_t*)errs)[s] = (uint8_t)e;
+            else if (ew == 2)
+                ((uint16_t*)errs)[s] = (uint16_t)e;
+            else
+                errs[s] = e;
+        }
     };
     auto err_get = [&](uint32_t s) -> uint32_t {
+        if constexpr (PK) return 0u;
         return ew == 1 ? (uint32_t)((const uint8_t*)errs)[s]
                        : ew == 2 ? (uint32_t)((const uint16_t*)errs)[s] : errs[s];
     };
@@ -744,7 +751,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
     // buckets per item: three in the LDS classes above k = 1024 (the layout's
     // table is sized for them), two elsewhere
     constexpr int NCH = (!G && P >= 32) ? 3 : 2;
-    if (L.choices != (uint32_t)NCH) {  // a layout built for another table shape
+    if (L.choices != (uint32_t)NCH || PK != (L.err_bytes == 0u)) {  // a layout built for another table shape
         if (lane == 0) {
             *o_size = kBlockFailed;
             *o_min = 0;
@@ -810,7 +817,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
             // move counters back to a bucket with room (deletions free slots
             // all the time).  A counter at the minimum level stays: it may be
             // listed as a victim by slot.
-            const bool cand = slive && (!full || c != m);
+            const bool cand = slive && (!full || (c & cmask) != m);
             if (ballot(cand)) {
                 const uint32_t s1 = home_bucket(skey, NB, hk), s2 = alt_bucket(skey, NB, s1, hk);
                 const uint32_t s3 = bucket3(skey, s1, s2);
@@ -1015,7 +1022,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
             // at most one pass over the listed entries plus one rebuild
             uint32_t guard = list_len / kWave + 3;
             for (;;) {
-                vv = vinb && vcnt == m;
+                vv = vinb && (vcnt & cmask) == m;
                 vmask = ballot(vv);
                 if (vmask) break;
                 if (guard-- == 0) {
@@ -1102,7 +1109,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
                 if (vr < rp)
                     table[vs] = empty_entry<NCH>(ekey, vs);
                 else
-                    words[2 * vs + 1] = m;
+                    words[2 * vs + 1] = vcnt;  // its count word as fetched: count m (and its error)
             }
             wave_sync();
         }
@@ -1110,7 +1117,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
         if (newf) {
             if (in) {
                 err_put(hp, full ? m : 0u);
-                table[hp] = make_entry(x, full ? m + 1u : 1u);
+                table[hp] = make_entry(x, full ? (PK ? (m << kCountBits) | (m + 1u) : m + 1u) : 1u);
             } else {
                 table[hp] = empty_entry<NCH>(ekey, hp);
             }
@@ -1169,9 +1176,9 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
         if (live) {
             const uint32_t o = outn + mbcnt(bm);
             o_item[o] = (uint32_t)e;
-            o_cnt[o] = c;
-            o_err[o] = err_get(s);
-            mn = min(mn, c);
+            o_cnt[o] = c & cmask;
+            o_err[o] = PK ? c >> kCountBits : err_get(s);
+            mn = min(mn, c & cmask);
         }
         outn = uniform(outn + popc64(bm));
     }
@@ -1185,7 +1192,7 @@ __device__ __forceinline__ uint32_t summarize_block(const uint32_t* __restrict__
 
 // A block under the attempts' hash functions in turn; after the last one
 // overflows, the block is marked failed (the caller sees a device error).
-template <int P, bool G, bool EB = false>
+template <int P, bool G, bool PK = false>
 __device__ __forceinline__ void summarize_block_any(const uint32_t* __restrict__ items, uint64_t n, uint64_t begin,
                                                     uint64_t end, const ChunkLayout& L, int vec_ok,
                                                     unsigned char* sb, unsigned char* lds,
@@ -1193,7 +1200,7 @@ __device__ __forceinline__ void summarize_block_any(const uint32_t* __restrict__
                                                     uint32_t* __restrict__ o_cnt, uint32_t* __restrict__ o_err,
                                                     uint32_t* __restrict__ o_size, uint32_t* __restrict__ o_min) {
     for (uint32_t attempt = 0; attempt < kHashAttempts; ++attempt) {
-        if (summarize_block<P, G, EB>(items, n, begin, end, L, vec_ok, sb, lds, errs, o_item, o_cnt, o_err, o_size,
+        if (summarize_block<P, G, PK>(items, n, begin, end, L, vec_ok, sb, lds, errs, o_item, o_cnt, o_err, o_size,
                                       o_min, hash_keys(attempt)) == kDone)
             return;
         wave_sync();  // the next attempt clears the table this one used
@@ -1206,9 +1213,9 @@ __device__ __forceinline__ void summarize_block_any(const uint32_t* __restrict__
 
 // One wave per block c of C: [floor(c n / C), floor((c+1) n / C)) (Algorithm
 // 1's block bounds, 64-bit products, n < 2^32).  G: state slab gstate +
-// c * state_bytes.  Error scratch of block c: errs + c * err_stride.  EB:
-// the layout stores errors in 1 byte.
-template <int P, bool G, bool EB>
+// c * state_bytes.  Error scratch of block c: errs + c * err_stride.  PK:
+// the layout packs each error in its counter's count word (no scratch).
+template <int P, bool G, bool PK>
 __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __restrict__ items, uint64_t n,
                                                            uint32_t chunks, ChunkLayout L, int vec_ok,
                                                            uint32_t* __restrict__ o_item,
@@ -1224,7 +1231,7 @@ __global__ __launch_bounds__(64) void chunk_summary_kernel(const uint32_t* __res
     const uint64_t begin = (uint64_t)c * n / chunks;
     const uint64_t end = (uint64_t)(c + 1) * n / chunks;
     const uint64_t ob = (uint64_t)c * L.k;
-    summarize_block_any<P, G, EB>(items, n, begin, end, L, vec_ok, sb, smem, errs + (size_t)c * L.err_stride,
+    summarize_block_any<P, G, PK>(items, n, begin, end, L, vec_ok, sb, smem, errs + (size_t)c * L.err_stride,
                                   o_item + ob, o_cnt + ob, o_err + ob, o_size + c, o_min + c);
 }
 
@@ -1315,26 +1322,25 @@ extern "C" int pss_debug_kstats(unsigned long long* out, int reset) {
 }
 #endif
 
-template <int P, bool G, bool EB>
+template <int P, bool G, bool PK>
 static hipError_t launch_pe(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L, int vec_ok,
                             const BlockSummaries& out, unsigned char* gstate, uint32_t* errs, hipStream_t stream) {
     (void)hipGetLastError();  // a stale error of an earlier, unrelated call is not this launch's
-    hipFuncSetAttribute((const void*)chunk_summary_kernel<P, G, EB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipFuncSetAttribute((const void*)chunk_summary_kernel<P, G, PK>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)L.lds_bytes);
-    hipLaunchKernelGGL((chunk_summary_kernel<P, G, EB>), dim3(chunks), dim3(64), L.lds_bytes, stream, d_items, n,
+    hipLaunchKernelGGL((chunk_summary_kernel<P, G, PK>), dim3(chunks), dim3(64), L.lds_bytes, stream, d_items, n,
                        chunks, L, vec_ok, out.item, out.cnt, out.err, out.size, out.min, gstate, errs);
     return hipGetLastError();
 }
 
-// 1-byte errors (the common case: blocks below 255 k items) get their own
-// instance of the LDS-state kernels up to k = 1024, which issue VALU
-// instructions most of the time (2% faster there; the k = 2000 instance,
-// bound by latency, gains nothing from it)
+// Errors packed in the count words (the common case: blocks of fewer than
+// 2^22 items and at most 1022 k) get their own instance of the LDS-state
+// kernels, with no error scratch and no width switch in the window loop
 template <int P, bool G>
 static hipError_t launch_p(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L, int vec_ok,
                            const BlockSummaries& out, unsigned char* gstate, uint32_t* errs, hipStream_t stream) {
-    if constexpr (!G && P < 32) {
-        if (L.err_bytes == 1) return launch_pe<P, G, true>(d_items, n, chunks, L, vec_ok, out, gstate, errs, stream);
+    if constexpr (!G) {
+        if (L.err_bytes == 0) return launch_pe<P, G, true>(d_items, n, chunks, L, vec_ok, out, gstate, errs, stream);
     }
     return launch_pe<P, G, false>(d_items, n, chunks, L, vec_ok, out, gstate, errs, stream);
 }
@@ -1364,7 +1370,7 @@ hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t ch
     const int vec_ok = ((uintptr_t)d_items & 15u) == 0;
     if (chunks == 0) return hipErrorInvalidValue;
     // blocks hold at most ceil(n / chunks) items
-    const ChunkLayout L = L0.with_error_width((n + chunks - 1) / chunks);
+    const ChunkLayout L = L0.with_error_width((n + chunks - 1) / chunks, true);
     if (!errs) return hipErrorInvalidValue;
     if (L.global_state) {
         if (!gstate) return hipErrorInvalidValue;

@@ -63,6 +63,14 @@ constexpr uint32_t kStash = 64;
 constexpr uint64_t kStreamBound = (1ull << 32) - 128;
 // The level sort's histogram: 257 words.
 constexpr uint32_t kHistBytes = 4 * 257;
+// A counter's count word may carry its error above the count: the count in
+// the low kCountBits bits, the error (at most kPackedErrMax) above them, so
+// that packed words stay below the window tags.
+constexpr uint32_t kCountBits = 22;
+constexpr uint32_t kCountMask = (1u << kCountBits) - 1u;
+constexpr uint32_t kPackedErrMax = 1022;
+static_assert((((uint64_t)kPackedErrMax << kCountBits) | kCountMask) < kStreamBound,
+              "packed count words stay below the window tags");
 
 PSS_HD inline uint32_t next_pow2(uint32_t v) {
     uint32_t p = 1;
@@ -105,8 +113,9 @@ struct ChunkLayout {
     uint32_t lds_bytes;
     // per-block error scratch in device memory: one error per slot, blocks
     // err_stride words apart (a multiple of 32: each block starts a cache
-    // line); err_bytes per error (4, or 2 / 1 by with_error_width)
-    uint32_t err_stride, err_bytes;
+    // line); err_bytes per error (4, or 2 / 1 by with_error_width; 0: the
+    // errors are packed in the count words and count_mask selects the count)
+    uint32_t err_stride, err_bytes, count_mask;
     uint32_t choices;  // buckets per item (hash_choices)
 
     // Default hash slots per counter (x16) for tables with `choices` buckets
@@ -164,6 +173,7 @@ struct ChunkLayout {
         L.lds_bytes = l;
         L.err_stride = (L.slots + 31u) & ~31u;
         L.err_bytes = 4;
+        L.count_mask = 0xFFFFFFFFu;
         return L;
     }
 
@@ -171,11 +181,20 @@ struct ChunkLayout {
     // of at most max_block items: an error is a count of the minimum level at
     // an install, at most max_block / k.  Narrow errors shrink a block's
     // scratch footprint, so fewer of its lines are written back to memory
-    // while the input stream passes through the L2.
-    PSS_HD ChunkLayout with_error_width(uint64_t max_block) const {
+    // while the input stream passes through the L2.  With allow_packed and the
+    // state in LDS, blocks whose counts fit kCountBits bits and whose errors
+    // are at most kPackedErrMax keep each error in its counter's count word
+    // (err_bytes 0): no scratch at all.
+    PSS_HD ChunkLayout with_error_width(uint64_t max_block, bool allow_packed = false) const {
         ChunkLayout R = *this;
         const uint64_t top = max_block / k;
+        if (allow_packed && !global_state && max_block <= kCountMask && top <= kPackedErrMax) {
+            R.err_bytes = 0;
+            R.count_mask = kCountMask;
+            return R;
+        }
         R.err_bytes = top < 255u ? 1u : top < 65535u ? 2u : 4u;
+        R.count_mask = 0xFFFFFFFFu;
         return R;
     }
 

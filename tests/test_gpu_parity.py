@@ -87,6 +87,28 @@ def test_whole_summary_equals_oracle_summary(B, ctx):
         s.close()
 
 
+@pytest.mark.parametrize("k,n,C", [(64, 65471, 1), (64, 65472, 1), (64, 130942, 2),
+                                   (4096, 4190207, 1), (4096, 4190208, 1)])
+def test_error_packing_bounds(B, ctx, k, n, C):
+    # errors ride in the count words while blocks hold fewer than 2^22 items
+    # and floor(block / k), the largest error, is at most 1022: blocks of
+    # 1023 k - 1 items pack, 1023 k do not (with k <= 4096 in LDS this bound
+    # comes before the count bound).  A long run of one id (counts up to
+    # half the block) and a uniform tail (errors at their largest).
+    rng = np.random.default_rng(k + n + C)
+    items = np.concatenate([np.full(n // 2, 12345, dtype=np.uint32),
+                            rng.integers(0, 1 << 32, n - n // 2, dtype=np.uint64).astype(np.uint32)])
+    say("error packing k=%d n=%d C=%d" % (k, n, C))
+    blocks = B.pss_block_summaries(ctx, dev(items), k, C, list(range(C)))
+    ref = O.chunk_summaries(items, k, C)
+    for c in range(C):
+        ent, mn = blocks[c]
+        assert sorted(B.to_tuples(ent)) == sorted(O.to_tuples(ref[c].entries)), (k, n, C, c)
+        assert mn == ref[c].m, (k, n, C, c)
+    got, _ = B.pss_run(ctx, dev(items), k=k, chunks=C)
+    assert B.to_tuples(got) == O.to_tuples(O.run(items, k, C))
+
+
 def _rand_stream(rng, n):
     kind = rng.choice(["few", "zipf", "uniform", "same", "edge", "roundrobin"])
     if kind == "few":

@@ -49,6 +49,16 @@ int main() {
                L.with_error_width(65535ull * k).err_bytes);
     }
     printf("\n");
+    // packed errors: err_bytes and count mask either side of the bounds, LDS and device-memory state
+    for (unsigned k : {64u, 4096u, 10000u}) {
+        const ChunkLayout L = ChunkLayout::make(k, k > 4096);
+        for (unsigned long long mb : {1023ull * k - 1, 1023ull * k, (unsigned long long)kCountMask,
+                                      (unsigned long long)kCountMask + 1}) {
+            const ChunkLayout P = L.with_error_width(mb, true), Q = L.with_error_width(mb);
+            printf("%u %llu %u %u %u %u ", k, mb, P.err_bytes, P.count_mask, Q.err_bytes, Q.count_mask);
+        }
+    }
+    printf("\n");
     printf("%u %u %u %llu %u %u\n", kBucketSlots, kStash, kHistBytes, (unsigned long long)kStreamBound, kRing, kLdsUnit);
     for (unsigned b : {1u, 1280u, 1281u, 11520u, 11600u, 32000u, 32608u})
         printf("%u ", lds_waves(163840, b));
@@ -82,10 +92,13 @@ def layouts(tmp_path_factory):
     assert cc.returncode == 0, cc.stderr
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines()
     c = {"ewidth": [int(v) for v in out[1].split()]}
-    consts = [int(v) for v in out[2].split()]
+    pk = [int(v) for v in out[2].split()]
+    c["packing"] = [dict(zip(["k", "mb", "pbytes", "pmask", "bytes", "mask"], pk[i:i + 6]))
+                    for i in range(0, len(pk), 6)]
+    consts = [int(v) for v in out[3].split()]
     c.update(zip(["bucket", "stash", "hist", "bound", "ring", "unit"], consts))
-    c["waves"] = [int(v) for v in out[3].split()]
-    f = [int(v) for v in out[4].split()]
+    c["waves"] = [int(v) for v in out[4].split()]
+    f = [int(v) for v in out[5].split()]
     c["freq"] = [dict(zip(["k", "ch", "ch_ss", "nb", "nb_ss", "slots", "ring", "lds", "waves"], f[i:i + 9]))
                  for i in range(0, len(f), 9)]
     return json.loads(out[0]), c
@@ -196,3 +209,19 @@ def test_frequent_layout_shares_the_table_shape(layouts):
         if 1024 < r["k"] <= 2048:
             assert r["ch"] == 3 and r["waves"] >= 7, r
     assert {r["k"]: r["waves"] for r in c["freq"]}[2000] == 7
+
+
+def test_errors_pack_into_count_words_only_within_bounds(layouts):
+    # packed (err_bytes 0, counts in the low 22 bits) when the state is in
+    # LDS, blocks hold at most 2^22 - 1 items and floor(block / k) <= 1022;
+    # never unless the caller allows it, never with the state in device memory
+    _, c = layouts
+    full, low22 = 0xFFFFFFFF, (1 << 22) - 1
+    for r in c["packing"]:
+        want = r["k"] <= 4096 and r["mb"] <= low22 and r["mb"] // r["k"] <= 1022
+        assert (r["pbytes"], r["pmask"]) == ((0, low22) if want else (r["bytes"], full)), r
+        assert r["bytes"] in (1, 2, 4) and r["mask"] == full, r
+    by = {(r["k"], r["mb"]): r["pbytes"] for r in c["packing"]}
+    assert by[(64, 1023 * 64 - 1)] == 0 and by[(64, 1023 * 64)] == 2
+    assert by[(4096, 1023 * 4096 - 1)] == 0 and by[(4096, 1023 * 4096)] == 2
+    assert all(by[(10000, mb)] != 0 for (k, mb) in by if k == 10000)

@@ -109,6 +109,28 @@ def test_error_packing_bounds(B, ctx, k, n, C):
     assert B.to_tuples(got) == O.to_tuples(O.run(items, k, C))
 
 
+@pytest.mark.parametrize("k,every", [(500, 733), (2000, 4001)])
+def test_largest_id_in_large_levels(B, ctx, k, every):
+    # the level sort compares ids alone and pads a lane's registers with the
+    # largest key; the id 0xFFFFFFFF, rarer than the minimum count grows in a
+    # uniform stream, is evicted and reinstalled over and over and keeps
+    # landing in levels of hundreds of counters
+    rng = np.random.default_rng(k)
+    n = 400000
+    items = rng.integers(0, 0xFFFFFFFF, n, dtype=np.uint64).astype(np.uint32)
+    items[::every] = 0xFFFFFFFF
+    for C in (1, 3):
+        say("largest id k=%d C=%d" % (k, C))
+        blocks = B.pss_block_summaries(ctx, dev(items), k, C, list(range(C)))
+        ref = O.chunk_summaries(items, k, C)
+        for c in range(C):
+            ent, mn = blocks[c]
+            assert sorted(B.to_tuples(ent)) == sorted(O.to_tuples(ref[c].entries)), (k, C, c)
+            assert mn == ref[c].m, (k, C, c)
+        got, _ = B.pss_run(ctx, dev(items), k=k, chunks=C)
+        assert B.to_tuples(got) == O.to_tuples(O.run(items, k, C))
+
+
 def _rand_stream(rng, n):
     kind = rng.choice(["few", "zipf", "uniform", "same", "edge", "roundrobin"])
     if kind == "few":

@@ -103,6 +103,19 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
     }
     const uint32_t nc = n1 + n2;
 
+    // a thread's first two S1 entries are loaded now, their latency hidden
+    // behind staging and hashing S2
+    uint32_t px[2];
+    C1 pc[2], pe[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const uint32_t i = tid + (uint32_t)r * NT;
+        const bool in = i < n1;
+        px[r] = in ? i1[i] : 0u;
+        pc[r] = in ? c1[i] : (C1)0;
+        pe[r] = in ? e1[i] : (C1)0;
+    }
+
     // stage S2 as candidates [n1, n1 + n2): items only in S2 get + m1
     for (uint32_t j = tid; j < n2; j += NT) {
         ci[n1 + j] = i2[j];
@@ -118,8 +131,8 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
     }
     __syncthreads();
     // S1 entries: Find in S2, add both estimates (and retire S2's), or + m2
-    for (uint32_t i = tid; i < n1; i += NT) {
-        const uint32_t x = i1[i];
+    for (uint32_t i = tid, r = 0; i < n1; i += NT, ++r) {
+        const uint32_t x = r == 0 ? px[0] : r == 1 ? px[1] : i1[i];
         uint32_t h = hash_slot(x, hbits);
         int32_t found = -1;
         for (;;) {
@@ -131,7 +144,8 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
             }
             h = (h + 1) & hmask;
         }
-        CO c = (CO)c1[i], e = (CO)e1[i];
+        CO c = r == 0 ? (CO)pc[0] : r == 1 ? (CO)pc[1] : (CO)c1[i];
+        CO e = r == 0 ? (CO)pe[0] : r == 1 ? (CO)pe[1] : (CO)e1[i];
         if (found >= 0) {
             c += cc[n1 + found] - m1;
             e += ce[n1 + found] - m1;
@@ -176,6 +190,11 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
     uint32_t ro[5], ra[5];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
+        if (sizeof(CO) == 4 && (j == 1 || j == 3)) {  // high words of 32-bit counts: unused
+            ro[j] = 0u;
+            ra[j] = ~0u;
+            continue;
+        }
         ro[j] = wave_or_u32(wo[j]);
         ra[j] = wave_and_u32(wa[j]);
     }
@@ -324,7 +343,7 @@ __device__ void combine_node(const uint32_t* i1, const C1* c1, const C1* e1, uin
         __syncthreads();  // the table is read before the next segment rewrites it
     }
     // minimum of the result: 0 unless all k counters are used
-    CO wmin = wave_min_u64((uint64_t)local_min);
+    const CO wmin = sizeof(CO) == 4 ? (CO)wave_min_u32((uint32_t)local_min) : (CO)wave_min_u64((uint64_t)local_min);
     uint64_t* red = (uint64_t*)(small + L.off_red);
     if (lane_id() == 0) red[tid / kWave] = (uint64_t)wmin;
     __syncthreads();

@@ -244,14 +244,71 @@ __device__ __forceinline__ void lane_merge(uint64_t (&v)[Q]) {
     }
 }
 
+// Bitonic merge of registers [OFF, OFF + W) of a lane (a bitonic sequence)
+// into ascending order.
+template <int OFF, int W, int Q>
+__device__ __forceinline__ void lane_merge_range(uint64_t (&v)[Q]) {
+#pragma unroll
+    for (int stride = W / 2; stride > 0; stride >>= 1) {
+#pragma unroll
+        for (int j = OFF; j < OFF + W; ++j) {
+            if (((j - OFF) & stride) == 0) {
+                const int j2 = j + stride;
+                const uint64_t a = v[j], b = v[j2];
+                v[j] = a < b ? a : b;
+                v[j2] = a < b ? b : a;
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// One pass that sorts lane-sorted runs whose disorder across each lane
+// boundary lies within W keys on either side (W <= Q / 2, so a lane's head
+// and tail regions are disjoint): every lane merges its last W keys with the
+// next lane's first W, keeping the W smallest, and its first W with the
+// previous lane's last W, keeping the W largest.  All neighbour keys are
+// read before any register changes.
+template <int W, int Q>
+__device__ __forceinline__ void boundary_merge(uint64_t (&v)[Q], uint32_t lane) {
+    static_assert(2 * W <= Q, "head and tail regions must not overlap");
+    const bool has_up = lane + 1 < kWave, has_dn = lane > 0;
+    const uint32_t up = has_up ? lane + 1 : lane, dn = has_dn ? lane - 1 : lane;
+    uint64_t nh[W], pt[W];  // the next lane's head, the previous lane's tail
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        nh[j] = shfl_u64(v[j], up);
+        pt[j] = shfl_u64(v[Q - W + j], dn);
+    }
+    // tail: my ascending last W against the next lane's head read in reverse
+    // (a bitonic sequence); its lower half holds the W smallest
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const uint64_t a = v[Q - W + j], b = nh[W - 1 - j];
+        v[Q - W + j] = has_up && b < a ? b : a;
+    }
+    // head: the previous lane's tail in reverse against my first W; the upper
+    // half holds the W largest
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const uint64_t a = v[j], b = pt[W - 1 - j];
+        v[j] = has_dn && b > a ? b : a;
+    }
+    lane_merge_range<Q - W, W>(v);
+    lane_merge_range<0, W>(v);
+}
+
 // Lane l takes positions [l Q, (l+1) Q) of list (slots, in an order where
 // only entries of one bucket can be out of order; each slot's id is read
 // from the table), sorts them in registers by (id, slot), and odd-even merges between
 // neighbouring lanes (the lower lane keeping the smaller half) finish the
 // order; the wave stops as soon as every lane's last key is at most its
 // neighbour's first, after at most 64 rounds (odd-even transposition over 64
-// blocks sorts any input).  Out of line: its registers stay apart from the
-// caller's.
+// blocks sorts any input).  Before the rounds, when every boundary's disorder
+// spans at most Q / 2 keys on each side (a bucket straddling it is short,
+// the usual case at Q <= 16), one boundary_merge pass sorts the whole list
+// and the rounds find nothing to do.  Out of line: its registers stay apart
+// from the caller's.
 template <int Q>
 __device__ __attribute__((noinline)) void merge_runs(lds_u16* list, const LdsIds ids, uint32_t len, uint32_t lane) {
     uint64_t v[Q];
@@ -264,6 +321,35 @@ __device__ __attribute__((noinline)) void merge_runs(lds_u16* list, const LdsIds
     }
     lane_sort<Q>(v);
     const uint32_t up = lane + 1 < kWave ? lane + 1 : lane;
+    if constexpr (Q >= 4 && Q <= 16) {
+        // disorder at the boundaries: my keys above the next lane's first,
+        // my keys below the previous lane's last (at Q = 32 a straddling
+        // bucket of ~8 usually exceeds the widths kept here, and the pass
+        // only added registers: measured 2% slower at k = 2000)
+        const uint32_t dn = lane > 0 ? lane - 1 : lane;
+        const uint64_t next_first = shfl_u64(v[0], up), prev_last = shfl_u64(v[Q - 1], dn);
+        uint32_t rt = 0, rh = 0;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            rt += (lane + 1 < kWave && v[j] > next_first) ? 1u : 0u;
+            rh += (lane > 0 && v[j] < prev_last) ? 1u : 0u;
+        }
+        const uint32_t r = wave_max_u32(rt > rh ? rt : rh);
+        // widths up to Q / 2; larger disorder goes to the rounds
+        if (r > 0u && r <= (uint32_t)Q / 2u) {
+            if (r <= 1u)
+                boundary_merge<1>(v, lane);
+            else if (r <= 2u)
+                boundary_merge<2>(v, lane);
+            else if constexpr (Q >= 8) {
+                if (r <= 4u)
+                    boundary_merge<4>(v, lane);
+                else if constexpr (Q >= 16) {
+                    if (r <= 8u) boundary_merge<8>(v, lane);
+                }
+            }
+        }
+    }
     for (uint32_t round = 0; round < kWave; ++round) {
         const uint64_t next_first = shfl_u64(v[0], up);
         if (ballot(lane + 1 < kWave && v[Q - 1] > next_first) == 0) break;

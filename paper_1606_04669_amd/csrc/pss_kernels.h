@@ -42,7 +42,8 @@ struct DevEntry {
 ChunkLayout chunk_layout(uint32_t k, size_t lds_max);
 // gstate: chunks * L.state_bytes bytes of device memory when L.global_state;
 // errs: chunks * L.err_stride words of device memory (error scratch; the
-// launch stores each error in the fewest bytes that hold every error of its
+// launch packs each error in its counter's count word when its blocks allow
+// it, else stores it in the fewest bytes that hold every error of its
 // blocks, ChunkLayout::with_error_width).  chunks >= 1.
 hipError_t launch_chunk_summary(const uint32_t* d_items, uint64_t n, uint32_t chunks, const ChunkLayout& L,
                                 const BlockSummaries& out, unsigned char* gstate, uint32_t* errs,

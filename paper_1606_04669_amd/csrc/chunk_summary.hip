@@ -321,11 +321,9 @@ __device__ __attribute__((noinline)) void merge_runs(lds_u16* list, const LdsIds
     }
     lane_sort<Q>(v);
     const uint32_t up = lane + 1 < kWave ? lane + 1 : lane;
-    if constexpr (Q >= 4 && Q <= 16) {
+    if constexpr (Q >= 4 && Q <= 32) {
         // disorder at the boundaries: my keys above the next lane's first,
-        // my keys below the previous lane's last (at Q = 32 a straddling
-        // bucket of ~8 usually exceeds the widths kept here, and the pass
-        // only added registers: measured 2% slower at k = 2000)
+        // my keys below the previous lane's last
         const uint32_t dn = lane > 0 ? lane - 1 : lane;
         const uint64_t next_first = shfl_u64(v[0], up), prev_last = shfl_u64(v[Q - 1], dn);
         uint32_t rt = 0, rh = 0;
@@ -335,7 +333,8 @@ __device__ __attribute__((noinline)) void merge_runs(lds_u16* list, const LdsIds
             rh += (lane > 0 && v[j] < prev_last) ? 1u : 0u;
         }
         const uint32_t r = wave_max_u32(rt > rh ? rt : rh);
-        // widths up to Q / 2; larger disorder goes to the rounds
+        // widths up to Q / 2 and 8 (wider ones hold more registers than the
+        // kernel can spare at Q = 32); larger disorder goes to the rounds
         if (r > 0u && r <= (uint32_t)Q / 2u) {
             if (r <= 1u)
                 boundary_merge<1>(v, lane);
@@ -398,7 +397,13 @@ __device__ __attribute__((noinline)) void merge_runs(lds_u16* list, const LdsIds
 template <int Q>
 __device__ __attribute__((noinline)) bool sort_level_buckets(lds_u16* list, const LdsIds ids, lds_u32* hist,
                                                              uint32_t len, uint32_t lane) {
-    constexpr int kDigitWords = (Q + 3) / 4;
+    // 8-bit digits; 9 at Q = 32 (levels of over 1024 counters, whose list
+    // area holds the 513-word histogram), so buckets stay short enough for
+    // merge_runs' boundary pass
+    constexpr uint32_t kDB = Q >= 32 ? 9u : 8u;
+    constexpr uint32_t kBins = 1u << kDB, kPer = kBins / kWave;
+    constexpr int kDpw = (int)(32u / kDB);  // digits per word
+    constexpr int kDigitWords = (Q + kDpw - 1) / kDpw;
     constexpr int kGroup = Q < 8 ? Q : 8;
     uint32_t sp[Q], dg[kDigitWords];
     uint32_t orv = 0u, andv = 0xFFFFFFFFu;
@@ -421,9 +426,9 @@ __device__ __attribute__((noinline)) bool sort_level_buckets(lds_u16* list, cons
     SORT_T(1);
     const uint32_t diff = wave_or_u32(orv) ^ wave_and_u32(andv);
     const uint32_t hb = 31u - (uint32_t)__builtin_clz(diff | 1u);
-    const uint32_t shift = hb >= 7u ? hb - 7u : 0u;
+    const uint32_t shift = hb >= kDB - 1u ? hb - (kDB - 1u) : 0u;
     wave_sync();  // the list is read: the histogram may now overwrite it
-    for (uint32_t i = lane; i < 257; i += kWave) hist[i] = 0u;
+    for (uint32_t i = lane; i < kBins + 1u; i += kWave) hist[i] = 0u;
     wave_sync();
 #pragma unroll
     for (int w = 0; w < kDigitWords; ++w) dg[w] = 0u;
@@ -432,8 +437,8 @@ __device__ __attribute__((noinline)) bool sort_level_buckets(lds_u16* list, cons
 #pragma unroll
         for (int j = j0; j < j0 + kGroup; ++j) {
             const uint32_t g = lane * Q + j;
-            const uint32_t d = (ids(sp[j]) >> shift) & 255u;
-            dg[j / 4] |= d << (8 * (j % 4));
+            const uint32_t d = (ids(sp[j]) >> shift) & (kBins - 1u);
+            dg[j / kDpw] |= d << (kDB * (uint32_t)(j % kDpw));
             const uint32_t pin =
                 (g < len) ? __hip_atomic_fetch_add(&hist[d], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) : 0u;
             sp[j] |= pin << 16;
@@ -442,8 +447,13 @@ __device__ __attribute__((noinline)) bool sort_level_buckets(lds_u16* list, cons
     }
     wave_sync();
     SORT_T(2);
-    const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
-    if (wave_max_u32(max(max(h0, h1), max(h2, h3))) > kMaxBucket) {
+    uint32_t hc[kPer], hmax = 0u;
+#pragma unroll
+    for (uint32_t t = 0; t < kPer; ++t) {
+        hc[t] = hist[kPer * lane + t];
+        hmax = max(hmax, hc[t]);
+    }
+    if (wave_max_u32(hmax) > kMaxBucket) {
         wave_sync();  // put the list back for the fallback
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
@@ -453,25 +463,29 @@ __device__ __attribute__((noinline)) bool sort_level_buckets(lds_u16* list, cons
         wave_sync();
         return false;
     }
-    // exclusive scan of the 256 counts: bucket d starts at hist[d]
-    const uint32_t sum = h0 + h1 + h2 + h3;
+    // exclusive scan of the counts: bucket d starts at hist[d]
+    uint32_t sum = 0u;
+#pragma unroll
+    for (uint32_t t = 0; t < kPer; ++t) sum += hc[t];
     uint32_t incl = sum;
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
         if ((int)lane >= off) incl += t;
     }
-    const uint32_t ex = incl - sum;
+    uint32_t ex = incl - sum;
     wave_sync();
-    hist[4 * lane] = ex;
-    hist[4 * lane + 1] = ex + h0;
-    hist[4 * lane + 2] = ex + h0 + h1;
-    hist[4 * lane + 3] = ex + h0 + h1 + h2;
+#pragma unroll
+    for (uint32_t t = 0; t < kPer; ++t) {
+        hist[kPer * lane + t] = ex;
+        ex += hc[t];
+    }
     wave_sync();
 #pragma unroll
     for (int j0 = 0; j0 < Q; j0 += kGroup) {
 #pragma unroll
         for (int j = j0; j < j0 + kGroup; ++j)  // the entry's place in bucket order
-            sp[j] = (sp[j] & 0xFFFFu) | ((hist[(dg[j / 4] >> (8 * (j % 4))) & 255u] + (sp[j] >> 16)) << 16);
+            sp[j] = (sp[j] & 0xFFFFu) |
+                    ((hist[(dg[j / kDpw] >> (kDB * (uint32_t)(j % kDpw))) & (kBins - 1u)] + (sp[j] >> 16)) << 16);
         __builtin_amdgcn_sched_barrier(0);
     }
     wave_sync();  // the histogram is read: list may now overwrite it

@@ -225,3 +225,17 @@ def test_errors_pack_into_count_words_only_within_bounds(layouts):
     assert by[(64, 1023 * 64 - 1)] == 0 and by[(64, 1023 * 64)] == 2
     assert by[(4096, 1023 * 4096 - 1)] == 0 and by[(4096, 1023 * 4096)] == 2
     assert all(by[(10000, mb)] != 0 for (k, mb) in by if k == 10000)
+
+
+def test_level_histogram_fits_the_list_area(layouts):
+    # the bucketed level sort lays its histogram over the list: 257 words,
+    # 513 for levels of over 1024 counters (9-bit digits), which only blocks
+    # with k > 1024 (32 sort lanes per k) list
+    rows, _ = layouts
+    for r in rows:
+        if r["g"]:
+            continue
+        area = r["tkey"] - r["list"]
+        assert area >= 4 * 257, r
+        if r["lanes"] >= 32:
+            assert area >= 4 * 513, r
